@@ -1,0 +1,295 @@
+/*
+ * oracle.c -- serial CPU reference for merge trees on regular grids.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is compiled into its own shared
+ * library (liboracle.so) and is loaded solely by the test suite, by the
+ * smoke check and by the CPU-baseline leg of the benchmark.  The product
+ * library never includes, links or calls it, and it shares no header, helper,
+ * table or constant generator with the HIP code.  The only thing the two
+ * agree on is the numbering of status codes, which each side writes down on
+ * its own.
+ *
+ * What it computes, each by its plain definition rather than by the
+ * parallel algorithm the product implements:
+ *
+ *  1. The merge tree of f on the grid graph (paper Sec. 2.1, "Merge trees").
+ *     The vertices are visited in increasing order of f; a union-find
+ *     structure tells, for each vertex, which of the three cases of that
+ *     section holds: it starts a new component (a local minimum), it joins
+ *     exactly one existing component, or it merges several.
+ *
+ *  2. The unique normalized and minimal triplet representation of that tree
+ *     (paper Sec. 2, "Triplet merge trees"): every vertex u is the first
+ *     vertex of exactly one triplet (u, s, v), stored as T[u] = (s, v), and v
+ *     is the deepest vertex of u's component of the sublevel set at the level
+ *     of s.  A global minimum of a component is the triplet (u, u, u); a
+ *     vertex of degree two in the merge tree is (u, u, v).  When several
+ *     components meet at a vertex, every component except the one holding
+ *     the deepest vertex ends there (its branch dies), which is what the
+ *     minimality condition forces.
+ *
+ *  3. The zero-dimensional persistence pairs, one per branch (paper Sec. 1):
+ *     the branch born at minimum u that dies at saddle s gives the point
+ *     (f(u), f(s)).  In triplet terms these are exactly the u with s != u.
+ *     Branches that never die (one per connected component) are counted as
+ *     roots and are not pairs.
+ *
+ *  4. The gradient, in double precision, of a loss written on the pairs with
+ *     respect to the field values: the birth value of a pair is f at its
+ *     minimum and the death value is f at its saddle, so the upstream
+ *     derivatives land on those two vertices (the scatter is the chain rule
+ *     and nothing else).
+ *
+ * Conventions.
+ *  - Grid: nx*ny*nz vertices stored C-contiguous as [nz][ny][nx]; vertex id
+ *    u = x + nx*(y + ny*z).  Edges join axis neighbours (6 in 3-D, 4 when
+ *    nz == 1, 2 when also ny == 1), the grid graph of Sec. 1.
+ *  - Order: u precedes w iff f(u) < f(w), or f(u) == f(w) and u < w.  The
+ *    comparison is the IEEE one, so -0.0 and +0.0 compare equal and the id
+ *    decides.  The paper writes strict inequalities assuming distinct values;
+ *    this index tie-break is the reading taken where values repeat.
+ *  - NaN anywhere is an error; +-Inf are ordinary values.
+ *  - Ids are 32-bit, so N must stay below 2^31 (Sec. 3.2 packs two 32-bit
+ *    ids into one word).
+ *
+ * All arithmetic on values is double; float input is converted exactly by
+ * the Python wrapper before it gets here.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* Status codes (same numbers as the product library, written out here). */
+#define OR_OK 0
+#define OR_ERR_INVALID_ARG (-1)
+#define OR_ERR_TOO_LARGE (-2)
+#define OR_ERR_NAN (-3)
+#define OR_ERR_CAPACITY (-4)
+#define OR_ERR_NOMEM (-8)
+
+/* The total order on vertices: value first, then id. */
+static int precedes(const double *f, int64_t a, int64_t b)
+{
+    return f[a] < f[b] || (f[a] == f[b] && a < b);
+}
+
+typedef struct {
+    double val;
+    uint32_t id;
+} keyed;
+
+static int cmp_keyed(const void *pa, const void *pb)
+{
+    const keyed *a = (const keyed *)pa;
+    const keyed *b = (const keyed *)pb;
+    if (a->val < b->val) return -1;
+    if (a->val > b->val) return 1;
+    return (a->id < b->id) ? -1 : (a->id > b->id) ? 1 : 0;
+}
+
+/* Union-find with union by size and path halving. */
+static uint32_t uf_find(uint32_t *parent, uint32_t x)
+{
+    while (parent[x] != x) {
+        parent[x] = parent[parent[x]];
+        x = parent[x];
+    }
+    return x;
+}
+
+static int validate(int64_t nx, int64_t ny, int64_t nz)
+{
+    if (nx < 1 || ny < 1 || nz < 1) return OR_ERR_INVALID_ARG;
+    if (nx >= (1LL << 31) || ny >= (1LL << 31) || nz >= (1LL << 31)) return OR_ERR_TOO_LARGE;
+    if (nx * ny >= (1LL << 31) || nx * ny * nz >= (1LL << 31)) return OR_ERR_TOO_LARGE;
+    return OR_OK;
+}
+
+/*
+ * Merge tree of f by the sorted union-find sweep of Sec. 2.1, written out as
+ * its triplet representation (Sec. 2).  T receives 2*N uint32: T[2u] = s,
+ * T[2u+1] = v.
+ */
+int oracle_merge_tree(const double *f, int64_t nx, int64_t ny, int64_t nz, uint32_t *T)
+{
+    int st = validate(nx, ny, nz);
+    if (st != OR_OK) return st;
+    if (!f || !T) return OR_ERR_INVALID_ARG;
+    const int64_t N = nx * ny * nz;
+    for (int64_t i = 0; i < N; ++i)
+        if (isnan(f[i])) return OR_ERR_NAN;
+
+    keyed *order = (keyed *)malloc((size_t)N * sizeof(keyed));
+    uint32_t *parent = (uint32_t *)malloc((size_t)N * sizeof(uint32_t));
+    uint32_t *size = (uint32_t *)malloc((size_t)N * sizeof(uint32_t));
+    uint32_t *deepest = (uint32_t *)malloc((size_t)N * sizeof(uint32_t)); /* valid at set roots */
+    if (!order || !parent || !size || !deepest) {
+        free(order); free(parent); free(size); free(deepest);
+        return OR_ERR_NOMEM;
+    }
+    for (int64_t i = 0; i < N; ++i) {
+        order[i].val = f[i];
+        order[i].id = (uint32_t)i;
+        parent[i] = (uint32_t)i;
+        size[i] = 1;
+        deepest[i] = (uint32_t)i;
+    }
+    qsort(order, (size_t)N, sizeof(keyed), cmp_keyed);
+
+    const int64_t sx = 1, sy = nx, sz = nx * ny;
+    for (int64_t i = 0; i < N; ++i) {
+        const int64_t u = order[i].id;
+        const int64_t x = u % nx, y = (u / nx) % ny, z = u / (nx * ny);
+        int64_t nb[6];
+        int nn = 0;
+        if (x > 0) nb[nn++] = u - sx;
+        if (x + 1 < nx) nb[nn++] = u + sx;
+        if (y > 0) nb[nn++] = u - sy;
+        if (y + 1 < ny) nb[nn++] = u + sy;
+        if (z > 0) nb[nn++] = u - sz;
+        if (z + 1 < nz) nb[nn++] = u + sz;
+
+        /* Components of the sublevel set below u that touch u: a neighbour
+           has already been swept exactly when it precedes u. */
+        uint32_t roots[6];
+        int nr = 0;
+        for (int k = 0; k < nn; ++k) {
+            if (!precedes(f, nb[k], u)) continue;
+            uint32_t r = uf_find(parent, (uint32_t)nb[k]);
+            int seen = 0;
+            for (int j = 0; j < nr; ++j) seen |= (roots[j] == r);
+            if (!seen) roots[nr++] = r;
+        }
+
+        if (nr == 0) {
+            /* Case (1): u is a local minimum and starts a component.  Until
+               that component merges into an older one, u is its deepest
+               vertex and its triplet is (u, u, u). */
+            T[2 * u] = (uint32_t)u;
+            T[2 * u + 1] = (uint32_t)u;
+            continue;
+        }
+
+        /* Cases (2) and (3).  The deepest vertex of the merged component is
+           the deepest of the deepest vertices of the parts. */
+        int best = 0;
+        for (int j = 1; j < nr; ++j)
+            if (precedes(f, deepest[roots[j]], deepest[roots[best]])) best = j;
+        const uint32_t m1 = deepest[roots[best]];
+
+        /* u itself: degree-two vertex (u, u, m1). */
+        T[2 * u] = (uint32_t)u;
+        T[2 * u + 1] = m1;
+
+        /* Every other part's branch, born at its deepest vertex m, ends at u
+           and joins the branch of m1: triplet (m, u, m1). */
+        for (int j = 0; j < nr; ++j) {
+            if (j == best) continue;
+            const uint32_t m = deepest[roots[j]];
+            T[2 * (int64_t)m] = (uint32_t)u;
+            T[2 * (int64_t)m + 1] = m1;
+        }
+
+        /* Union everything with u. */
+        uint32_t r = (uint32_t)u;
+        for (int j = 0; j < nr; ++j) {
+            uint32_t a = uf_find(parent, r), b = roots[j];
+            if (a == b) continue;
+            if (size[a] < size[b]) { uint32_t t = a; a = b; b = t; }
+            parent[b] = a;
+            size[a] += size[b];
+            r = a;
+        }
+        deepest[uf_find(parent, (uint32_t)u)] = m1;
+    }
+
+    free(order); free(parent); free(size); free(deepest);
+    return OR_OK;
+}
+
+/*
+ * Persistence pairs read off the triplets (Sec. 1: one point per branch).
+ * The branch born at u dies at s exactly when T[u] = (s, v) with s != u.
+ * Pairs are emitted in ascending birth id.  Returns the number of pairs (or a
+ * negative status); when it exceeds capacity nothing beyond capacity is
+ * written and the full count is still returned.  *n_roots (if not NULL)
+ * receives the number of triplets (u, u, u).
+ */
+int64_t oracle_pairs(const double *f, const uint32_t *T, int64_t N,
+                     uint32_t *birth, uint32_t *death, double *birth_val, double *death_val,
+                     int64_t capacity, int64_t *n_roots)
+{
+    if (!f || !T || N < 0) return OR_ERR_INVALID_ARG;
+    int64_t p = 0, roots = 0;
+    for (int64_t u = 0; u < N; ++u) {
+        const uint32_t s = T[2 * u], v = T[2 * u + 1];
+        if (s == (uint32_t)u) {
+            if (v == (uint32_t)u) ++roots;
+            continue;
+        }
+        if (p < capacity) {
+            birth[p] = (uint32_t)u;
+            death[p] = s;
+            birth_val[p] = f[u];
+            death_val[p] = f[s];
+        }
+        ++p;
+    }
+    if (n_roots) *n_roots = roots;
+    return p;
+}
+
+/*
+ * Chain rule for a loss written on the pair values: the birth value is f at
+ * the birth vertex and the death value is f at the death vertex, so
+ * grad[birth[k]] += gb[k] and grad[death[k]] += gd[k].  grad is accumulated
+ * into, in double.
+ */
+int oracle_pairs_scatter(int64_t N, const uint32_t *birth, const uint32_t *death,
+                         const double *gb, const double *gd, int64_t P, double *grad)
+{
+    if (!grad || (P > 0 && (!birth || !death || !gb || !gd))) return OR_ERR_INVALID_ARG;
+    for (int64_t k = 0; k < P; ++k) {
+        if ((int64_t)birth[k] >= N || (int64_t)death[k] >= N) return OR_ERR_INVALID_ARG;
+        grad[birth[k]] += gb[k];
+        grad[death[k]] += gd[k];
+    }
+    return OR_OK;
+}
+
+/*
+ * Topological-simplification loss on the persistence pairs of f:
+ * L = sum over pairs with (death - birth) < tau of (death - birth)^2, and,
+ * if grad is not NULL, dL/df written into grad (overwritten, length N).
+ * Returns the loss through *loss.  All in double.
+ */
+int oracle_topo_loss(const double *f, int64_t nx, int64_t ny, int64_t nz, double tau,
+                     double *loss, double *grad)
+{
+    int st = validate(nx, ny, nz);
+    if (st != OR_OK) return st;
+    const int64_t N = nx * ny * nz;
+    uint32_t *T = (uint32_t *)malloc((size_t)N * 2 * sizeof(uint32_t));
+    if (!T) return OR_ERR_NOMEM;
+    st = oracle_merge_tree(f, nx, ny, nz, T);
+    if (st != OR_OK) { free(T); return st; }
+
+    double L = 0.0;
+    if (grad) memset(grad, 0, (size_t)N * sizeof(double));
+    for (int64_t u = 0; u < N; ++u) {
+        const uint32_t s = T[2 * u];
+        if (s == (uint32_t)u) continue;
+        const double b = f[u], d = f[s];
+        const double pers = d - b;
+        if (!(pers < tau)) continue;
+        L += pers * pers;
+        if (grad) {
+            grad[u] += -2.0 * pers;
+            grad[s] += 2.0 * pers;
+        }
+    }
+    free(T);
+    *loss = L;
+    return OR_OK;
+}

@@ -1,0 +1,220 @@
+"""Interleaving simulator of the lock-free triplet merge tree algorithm.
+
+Test infrastructure.  It runs the parallel algorithm of Sec. 2 (Alg. 1: init,
+merge every edge, repair every vertex; Alg. 2 CAS; Alg. 3 Merge; Alg. 4
+Representative; Alg. 5 Repair) with each logical thread written as a Python
+generator that yields before every access to the shared map T.  A seeded
+scheduler picks which thread advances next, so every run is one sequentially
+consistent interleaving of the threads' atomic steps; phases are separated
+as in Alg. 1.
+
+Readings of the printed pseudocode that the simulator implements (and that
+the tests below pin against the oracle):
+
+- Descents stop at roots: a triplet (x, x, x) has no lower vertex to move to,
+  and following it would loop forever.
+- After a successful CAS that replaced a root (v, v, v), no displaced
+  triplet needs to be merged again; merging (u, v, v) again would assert a
+  connection at the level of v that does not hold.
+- Representative returns the last vertex reached by the chase (the deepest
+  vertex found), not the target stored in that vertex's triplet.
+
+Variants used by the GPU design, each checked to give the same unique T:
+
+- ``prelink``: every non-minimum first points at its lowest lower neighbour,
+  T[u] = (u, w(u)), which is the state reached by merging those edges one
+  after another in decreasing order of their upper vertex; the remaining
+  edges are merged as usual.
+- ``basins``: as prelink, with the pointer chains compressed to the minimum
+  z(u) reached by steepest descent, T[u] = (u, z(u)); an edge whose ends
+  descend to the same minimum is already implied and is skipped, and the
+  other edges are merged between the two minima, Merge(z(a), max(a, b), z(b)).
+"""
+from __future__ import annotations
+
+import random
+
+import numpy as np
+
+
+class LivelockError(RuntimeError):
+    pass
+
+
+def _keyer(flat):
+    def key(x):
+        return (float(flat[x]), int(x))
+    return key
+
+
+def grid_edges(shape):
+    """Axis edges of a C-order grid of the given numpy shape, as (a, b) id pairs."""
+    ids = np.arange(int(np.prod(shape))).reshape(shape)
+    edges = []
+    for ax in range(len(shape)):
+        if shape[ax] < 2:
+            continue
+        lo = [slice(None)] * len(shape)
+        hi = [slice(None)] * len(shape)
+        lo[ax] = slice(0, shape[ax] - 1)
+        hi[ax] = slice(1, shape[ax])
+        a = ids[tuple(lo)].ravel()
+        b = ids[tuple(hi)].ravel()
+        edges.extend(zip(a.tolist(), b.tolist()))
+    return edges
+
+
+def neighbours(shape):
+    nb = {u: [] for u in range(int(np.prod(shape)))}
+    for a, b in grid_edges(shape):
+        nb[a].append(b)
+        nb[b].append(a)
+    return nb
+
+
+# -- threads ---------------------------------------------------------------
+
+def merge_thread(T, key, u, s, v, root_guard=True, skip_root_remerge=True, cap=100000):
+    """Alg. 3 as a loop (its recursion is a tail call), yielding before each T access."""
+    ks = key(s)
+    for _ in range(cap):
+        yield
+        su, u1 = T[u]
+        u_root = (u1 == u) and (su == u)
+        if (not u_root or not root_guard) and key(su) < ks:
+            u = u1
+            continue
+        yield
+        sv, v1 = T[v]
+        v_root = (v1 == v) and (sv == v)
+        if (not v_root or not root_guard) and key(sv) < ks:
+            v = v1
+            continue
+        if u == v:
+            return
+        if key(v) < key(u):
+            u, v = v, u
+            su, u1, sv, v1 = sv, v1, su, u1
+        yield
+        if T[v] == (sv, v1):  # CAS, atomic in one scheduler step
+            T[v] = (s, u)
+            if skip_root_remerge and v1 == v and sv == v:
+                return
+            s, v = sv, v1
+            ks = key(s)
+        # CAS failed: start again with the same (u, s, v)
+    raise LivelockError("merge exceeded step cap")
+
+
+def repair_thread(T, key, u, return_last=True, cap=100000):
+    """Alg. 5 with Alg. 4 inlined; yields before each T access."""
+    yield
+    s, v = T[u]
+    ks = key(s)
+    x = u
+    sx, vx = s, v
+    for _ in range(cap):
+        if (vx == x and sx == x) or key(sx) > ks:
+            break
+        x = vx
+        yield
+        sx, vx = T[x]
+    else:
+        raise LivelockError("repair exceeded step cap")
+    r = x if return_last else vx
+    if r != u:
+        yield
+        T[u] = (s, r)
+
+
+def run_phase(threads, rng, max_steps=10_000_000):
+    live = list(threads)
+    steps = 0
+    while live:
+        i = rng.randrange(len(live))
+        try:
+            next(live[i])
+        except StopIteration:
+            live[i] = live[-1]
+            live.pop()
+        steps += 1
+        if steps > max_steps:
+            raise LivelockError("phase exceeded step cap")
+
+
+# -- the algorithm and its variants ---------------------------------------
+
+def steepest_lower(flat, shape):
+    key = _keyer(flat)
+    nb = neighbours(shape)
+    w = np.arange(flat.size)
+    for u in range(flat.size):
+        best = u
+        for x in nb[u]:
+            if key(x) < key(best):
+                best = x
+        w[u] = best
+    return w
+
+
+def simulate(f, seed=0, variant="paper", edge_order=None, serial=False,
+             root_guard=True, skip_root_remerge=True, return_last=True):
+    """Run Alg. 1 (or a variant) under one seeded interleaving; returns T [N, 2]."""
+    f = np.asarray(f)
+    shape = f.shape
+    flat = f.ravel().astype(np.float64)
+    N = flat.size
+    key = _keyer(flat)
+    rng = random.Random(seed)
+    edges = list(edge_order) if edge_order is not None else grid_edges(shape)
+    if edge_order is None:
+        rng.shuffle(edges)
+
+    T = [(u, u) for u in range(N)]
+    merges = []
+    if variant == "paper":
+        for a, b in edges:
+            hi, lo = (a, b) if key(b) < key(a) else (b, a)
+            merges.append((hi, hi, lo))
+    elif variant in ("prelink", "basins"):
+        w = steepest_lower(flat, shape)
+        for u in range(N):
+            T[u] = (u, int(w[u])) if w[u] != u else (u, u)
+        if variant == "prelink":
+            for a, b in edges:
+                hi, lo = (a, b) if key(b) < key(a) else (b, a)
+                if w[hi] == lo:
+                    continue  # already merged by the pre-link
+                merges.append((hi, hi, lo))
+        else:
+            z = w.copy()
+            for u in range(N):
+                x = u
+                while z[x] != x:
+                    x = z[x]
+                z[u] = x
+            for u in range(N):
+                if z[u] != u:
+                    T[u] = (u, int(z[u]))
+            for a, b in edges:
+                if z[a] == z[b]:
+                    continue  # implied by the two descents
+                hi = a if key(b) < key(a) else b
+                merges.append((int(z[a]), hi, int(z[b])))
+    else:
+        raise ValueError(variant)
+
+    def mk_merges():
+        return [merge_thread(T, key, u, s, v, root_guard, skip_root_remerge) for (u, s, v) in merges]
+
+    if serial:
+        for th in mk_merges():
+            for _ in th:
+                pass
+        for u in range(N):
+            for _ in repair_thread(T, key, u, return_last):
+                pass
+    else:
+        run_phase(mk_merges(), rng)
+        run_phase([repair_thread(T, key, u, return_last) for u in range(N)], rng)
+    return np.array(T, dtype=np.uint32)
