@@ -1,0 +1,188 @@
+/*
+ * mt.h -- C ABI of the MI355X triplet merge tree library (libmt.so).
+ *
+ * The library computes, on one AMD MI355X (gfx950), the merge tree of a
+ * float32 scalar field on a 1-D, 2-D or 3-D regular grid in the triplet
+ * representation of "Fast Merge Tree Computation via SYCL" (arXiv 2301.10838),
+ * Sec. 2, "Triplet merge trees": every vertex u owns exactly one triplet
+ * (u, s, v), stored as T[u] = (s, v), meaning that the branch born at u joins
+ * the branch of the deeper vertex v at the saddle s; (u, u, u) marks the
+ * global minimum of a connected component and (u, u, v) a vertex of degree
+ * two.  The stored representation is the unique normalized and minimal one
+ * (v is the deepest vertex of u's component of the sublevel set at the level
+ * of s), which is what makes results comparable bit for bit.  It also reads
+ * out the zero-dimensional persistence pairs, one per branch (Sec. 1), and
+ * scatters gradients of a loss on those pairs back onto the field.
+ *
+ * Conventions shared by every call:
+ *  - A field of nx*ny*nz values is C-contiguous [nz][ny][nx]; vertex id
+ *    u = x + nx*(y + ny*z).  A 2-D field has nz = 1, a 1-D field ny = nz = 1.
+ *    Edges join axis neighbours (6, 4 or 2 per vertex), the grid graph the
+ *    paper builds by connecting neighbouring grid points (Sec. 1).
+ *  - Vertices are ordered by value, ties by id: u precedes w iff
+ *    f[u] < f[w] or (f[u] == f[w] and u < w), with the IEEE comparison
+ *    (-0.0 == +0.0).  The paper's definitions use strict inequalities on
+ *    distinct values; the id tie-break is this library's reading for repeats.
+ *  - Ids are 32-bit (Sec. 3.2 packs a pair into one 64-bit word); a field,
+ *    or a whole batch, must hold fewer than 2^31 vertices.
+ *  - T is uint32[N][2] = (s, v): one 8-byte-aligned 64-bit word per vertex,
+ *    s in the low half.  Ids in every output are local to their field.
+ *  - Pointers marked (device) are device memory on the current HIP device,
+ *    allocated by the caller (hipMalloc, a torch tensor, ...); the caller owns
+ *    every buffer.  The library allocates no memory per call; it keeps only
+ *    cached graph plans, released by mt_release_caches.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Work is
+ *    enqueued asynchronously unless the call says it synchronizes.
+ *  - Every call returns an mt_status.  Host-side argument checks run before
+ *    anything is enqueued.  Conditions found on the device (NaN input, a
+ *    step cap exceeded, too small a pair capacity) are latched in a status
+ *    word inside the workspace and returned by the next synchronizing call
+ *    on that workspace (mt_persistence_pairs, mt_sync_status).
+ */
+#ifndef MT_H
+#define MT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MT_OK = 0,
+    MT_ERR_INVALID_ARG = -1, /* bad dims, null or misaligned pointer, bad count */
+    MT_ERR_TOO_LARGE = -2,   /* 2^31 vertices or more (32-bit ids, Sec. 3.2) */
+    MT_ERR_NAN = -3,         /* the field holds a NaN: no order exists */
+    MT_ERR_CAPACITY = -4,    /* more pairs than the output capacity */
+    MT_ERR_LIVELOCK = -5,    /* a merge or chase exceeded its step cap */
+    MT_ERR_WORKSPACE = -6,   /* workspace null or smaller than required */
+    MT_ERR_HIP = -7,         /* a HIP runtime call failed */
+    MT_ERR_INTERNAL = -8     /* a kernel met an out-of-range id (broken invariant); output invalid */
+} mt_status;
+
+/* Human-readable name of a status code (static string). */
+const char *mt_status_string(int status);
+
+/* Bytes of device workspace one field of nx*ny*nz vertices needs; 0 if the
+ * dims are invalid. */
+size_t mt_workspace_bytes(int64_t nx, int64_t ny, int64_t nz);
+
+/* Bytes of device workspace a batch needs.  dims (host) is int64[n_fields][3]
+ * = (nx, ny, nz) per field.  0 if any entry is invalid. */
+size_t mt_batch_workspace_bytes(const int64_t *dims, int32_t n_fields);
+
+/*
+ * mt_build -- merge tree of one field (paper Alg. 1, ComputeMergeTree).
+ *
+ * field     (device) float[nx*ny*nz], read only.
+ * triplets  (device) uint32[N][2], written: T[u] = (s, v) as described above.
+ * workspace (device) at least mt_workspace_bytes(nx, ny, nz) bytes, 256-byte
+ *           aligned; scratch for the call, and it carries the latched device
+ *           status to a following mt_persistence_pairs on the same workspace.
+ *
+ * Steps, all on `stream`, asynchronous:
+ *  1. every vertex points at its lowest lower neighbour (or at itself when it
+ *     is a local minimum, which is the initial triplet (u, u, u) of Alg. 1);
+ *     this is the state Alg. 3 reaches by merging those edges in decreasing
+ *     order of their upper vertex;
+ *  2. those chains are compressed to the minimum each vertex descends to;
+ *  3. every grid edge whose ends descend to different minima is merged with
+ *     the lock-free path merge of Alg. 3 (64-bit compare-and-swap, Alg. 2);
+ *     the others are already implied and need no merge;
+ *  4. repair (Alg. 4, 5) restores minimality, minima first, then every other
+ *     vertex.
+ * Errors: MT_ERR_INVALID_ARG, MT_ERR_TOO_LARGE, MT_ERR_WORKSPACE, MT_ERR_HIP
+ * synchronously; MT_ERR_NAN / MT_ERR_LIVELOCK latched in the workspace.
+ */
+int mt_build(const float *field, int64_t nx, int64_t ny, int64_t nz,
+             uint32_t *triplets, void *workspace, size_t ws_bytes, void *stream);
+
+/*
+ * mt_persistence_pairs -- zero-dimensional persistence pairs of a merge tree
+ * (Sec. 1: one point (f(a), f(b)) per branch from minimum a to saddle b).
+ *
+ * Reads only `field` and `triplets` (device): a pair is every u with
+ * T[u] = (s, v), s != u, emitted in ascending birth id u with death id s and
+ * values f[u], f[s] (bit copies).  Triplets (u, u, u) are the essential
+ * branches, one per connected component; they are counted in *n_roots.
+ *
+ * birth, death (device) uint32[capacity]; birth_val, death_val (device)
+ * float[capacity].  capacity >= ceil(N/2) always suffices.
+ * n_pairs (host, required) receives the number of pairs, also when it exceeds
+ * capacity (then only the first `capacity` are written and the call returns
+ * MT_ERR_CAPACITY).  n_roots (host) may be NULL.
+ * workspace: as for mt_build; pass the one mt_build used so its latched
+ * status (NaN, livelock) is reported here.
+ * Synchronizes `stream` once, to return the counts and the status.
+ */
+int mt_persistence_pairs(const float *field, const uint32_t *triplets,
+                         int64_t nx, int64_t ny, int64_t nz,
+                         uint32_t *birth, uint32_t *death, float *birth_val, float *death_val,
+                         int64_t capacity, int64_t *n_pairs, int64_t *n_roots,
+                         void *workspace, size_t ws_bytes, void *stream);
+
+/*
+ * mt_batch_build -- merge trees and pairs of many fields of uneven sizes in
+ * one graph launch.  This batching is not in the paper; each field gets
+ * exactly the triplets and pairs that mt_build + mt_persistence_pairs give it.
+ *
+ * fields    (device) the fields concatenated in order, float[sum N_i].
+ * dims      (host) int64[n_fields][3] = (nx, ny, nz) per field.
+ * triplets  (device) uint32[sum N_i][2], concatenated like `fields`; ids are
+ *           local to their field.
+ * birth, death, birth_val, death_val (device) [pair_capacity]: pairs of all
+ *           fields concatenated in field order, each field's in ascending
+ *           birth id, ids local to their field.
+ * pair_offsets (device) int64[n_fields + 1]: pairs of field i occupy
+ *           [pair_offsets[i], pair_offsets[i+1]); pair_offsets[n_fields] is
+ *           the total (it may exceed pair_capacity: MT_ERR_CAPACITY is then
+ *           latched and nothing past capacity is written).
+ * workspace (device) mt_batch_workspace_bytes(dims, n_fields) bytes.
+ * Asynchronous: the whole sequence is captured once per distinct argument
+ * set into a hipGraph and replayed with one hipGraphLaunch on `stream`.
+ * Read the latched status (and the total) with mt_sync_status.
+ */
+int mt_batch_build(const float *fields, const int64_t *dims, int32_t n_fields,
+                   uint32_t *triplets, uint32_t *birth, uint32_t *death,
+                   float *birth_val, float *death_val, int64_t pair_capacity,
+                   int64_t *pair_offsets, void *workspace, size_t ws_bytes, void *stream);
+
+/*
+ * mt_sync_status -- synchronize `stream` and return the status latched in
+ * `workspace` by the work enqueued before (MT_OK if none).  n_pairs and
+ * n_roots (host, may be NULL) receive the totals of the last pairs readout
+ * on that workspace.
+ */
+int mt_sync_status(const void *workspace, void *stream, int64_t *n_pairs, int64_t *n_roots);
+
+/*
+ * mt_pairs_backward -- adjoint of the pair readout.  A pair's birth value is
+ * f at its birth vertex and its death value is f at its death vertex, so for
+ * upstream gradients gb, gd:  grad[birth_k] += gb_k,  grad[death_k] += gd_k.
+ * (Not in the paper; it serves losses on persistence pairs, the use the
+ * paper's introduction motivates.)
+ *
+ * dims (host) int64[n_fields][3]; pair_offsets (device) int64[n_fields + 1]
+ * as written by mt_batch_build (for one field: {0, P}); birth, death (device)
+ * uint32, field-local ids; grad_birth, grad_death (device) float, one per
+ * pair; grad_field (device) float[sum N_i].  accumulate = 0 overwrites
+ * grad_field with the result, 1 adds to it.  Birth vertices never repeat;
+ * death vertices can (several branches may die at one saddle) and are summed
+ * with float atomics, so the rounding order of such sums is not fixed.
+ * pair_capacity bounds the number of pairs read.  Asynchronous.
+ */
+int mt_pairs_backward(const int64_t *dims, int32_t n_fields, const int64_t *pair_offsets,
+                      int64_t pair_capacity, const uint32_t *birth, const uint32_t *death,
+                      const float *grad_birth, const float *grad_death, float *grad_field,
+                      int accumulate, void *stream);
+
+/* Free cached graph plans (device and host memory they hold).  Not safe to
+ * call while another thread is inside the library. */
+void mt_release_caches(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MT_H */

@@ -1,0 +1,285 @@
+"""Python binding of libmt.so (ctypes): argument marshalling only.
+
+Every step of the merge-tree path runs in the library's HIP kernels; this
+module allocates torch tensors for outputs and workspaces, passes raw device
+pointers and the current HIP stream, and turns status codes into exceptions.
+It never falls back to another implementation: without the built library, or
+without a GPU, every call raises.
+
+Functions keep the C names: ``mt_build``, ``mt_persistence_pairs``,
+``mt_batch_build``, ``mt_pairs_backward``; ``MergeTreePairs`` wraps the batch
+build and the backward scatter as a ``torch.autograd.Function``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Sequence
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libmt.so")
+
+MT_OK = 0
+STATUS_NAMES = {
+    0: "MT_OK", -1: "MT_ERR_INVALID_ARG", -2: "MT_ERR_TOO_LARGE", -3: "MT_ERR_NAN", -4: "MT_ERR_CAPACITY",
+    -5: "MT_ERR_LIVELOCK", -6: "MT_ERR_WORKSPACE", -7: "MT_ERR_HIP", -8: "MT_ERR_INTERNAL",
+}
+EXPORTS = [
+    "mt_status_string", "mt_workspace_bytes", "mt_batch_workspace_bytes", "mt_build", "mt_persistence_pairs",
+    "mt_batch_build", "mt_sync_status", "mt_pairs_backward", "mt_release_caches",
+]
+
+
+class MTError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {STATUS_NAMES.get(status, status)}")
+        self.status = status
+
+
+_lib = None
+
+
+def load_library():
+    """Load libmt.so and declare its signatures (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I64, I32, SZ = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_size_t
+    lib.mt_status_string.argtypes = [ctypes.c_int]
+    lib.mt_status_string.restype = ctypes.c_char_p
+    lib.mt_workspace_bytes.argtypes = [I64, I64, I64]
+    lib.mt_workspace_bytes.restype = SZ
+    lib.mt_batch_workspace_bytes.argtypes = [P, I32]
+    lib.mt_batch_workspace_bytes.restype = SZ
+    lib.mt_build.argtypes = [P, I64, I64, I64, P, P, SZ, P]
+    lib.mt_build.restype = ctypes.c_int
+    lib.mt_persistence_pairs.argtypes = [P, P, I64, I64, I64, P, P, P, P, I64, P, P, P, SZ, P]
+    lib.mt_persistence_pairs.restype = ctypes.c_int
+    lib.mt_batch_build.argtypes = [P, P, I32, P, P, P, P, P, I64, P, P, SZ, P]
+    lib.mt_batch_build.restype = ctypes.c_int
+    lib.mt_sync_status.argtypes = [P, P, P, P]
+    lib.mt_sync_status.restype = ctypes.c_int
+    lib.mt_pairs_backward.argtypes = [P, I32, P, I64, P, P, P, P, P, ctypes.c_int, P]
+    lib.mt_pairs_backward.restype = ctypes.c_int
+    lib.mt_release_caches.argtypes = []
+    lib.mt_release_caches.restype = None
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, what: str):
+    if rc != MT_OK:
+        raise MTError(rc, what)
+
+
+def grid_dims(shape: Sequence[int]):
+    """(nx, ny, nz) of a C-order [nz][ny][nx] (or lower-rank) shape."""
+    shape = tuple(int(s) for s in shape)
+    if len(shape) == 1:
+        return shape[0], 1, 1
+    if len(shape) == 2:
+        return shape[1], shape[0], 1
+    if len(shape) == 3:
+        return shape[2], shape[1], shape[0]
+    raise ValueError("fields must be 1-D, 2-D or 3-D")
+
+
+def _stream_ptr(device: torch.device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _field(field: torch.Tensor) -> torch.Tensor:
+    if not isinstance(field, torch.Tensor) or field.device.type != "cuda":
+        raise TypeError("field must be a torch tensor on a HIP device")
+    if field.dtype != torch.float32:
+        raise TypeError("field must be float32")
+    return field.contiguous()
+
+
+def workspace_bytes(shape) -> int:
+    nx, ny, nz = grid_dims(shape)
+    return int(load_library().mt_workspace_bytes(nx, ny, nz))
+
+
+def alloc_workspace(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def mt_build(field: torch.Tensor, triplets: torch.Tensor | None = None,
+             workspace: torch.Tensor | None = None) -> torch.Tensor:
+    """Triplets T[u] = (s, v) of the merge tree of `field` (int32 [N, 2], uint32 bit patterns)."""
+    lib = load_library()
+    f = _field(field)
+    nx, ny, nz = grid_dims(f.shape)
+    N = nx * ny * nz
+    if triplets is None:
+        triplets = torch.empty((N, 2), dtype=torch.int32, device=f.device)
+    if workspace is None:
+        workspace = alloc_workspace(lib.mt_workspace_bytes(nx, ny, nz), f.device)
+    rc = lib.mt_build(f.data_ptr(), nx, ny, nz, triplets.data_ptr(), workspace.data_ptr(),
+                      workspace.numel(), _stream_ptr(f.device))
+    _check(rc, "mt_build")
+    return triplets
+
+
+def mt_persistence_pairs(field: torch.Tensor, triplets: torch.Tensor, capacity: int | None = None,
+                         workspace: torch.Tensor | None = None):
+    """(birth, death, birth_val, death_val, n_roots); ids int32, ascending birth id."""
+    lib = load_library()
+    f = _field(field)
+    nx, ny, nz = grid_dims(f.shape)
+    N = nx * ny * nz
+    if capacity is None:
+        capacity = N // 2 + 1
+    dev = f.device
+    birth = torch.empty(max(capacity, 1), dtype=torch.int32, device=dev)
+    death = torch.empty_like(birth)
+    bval = torch.empty(max(capacity, 1), dtype=torch.float32, device=dev)
+    dval = torch.empty_like(bval)
+    if workspace is None:
+        workspace = alloc_workspace(lib.mt_workspace_bytes(nx, ny, nz), dev)
+    n_pairs = ctypes.c_int64(0)
+    n_roots = ctypes.c_int64(0)
+    rc = lib.mt_persistence_pairs(f.data_ptr(), triplets.data_ptr(), nx, ny, nz, birth.data_ptr(),
+                                  death.data_ptr(), bval.data_ptr(), dval.data_ptr(), capacity,
+                                  ctypes.byref(n_pairs), ctypes.byref(n_roots), workspace.data_ptr(),
+                                  workspace.numel(), _stream_ptr(dev))
+    _check(rc, "mt_persistence_pairs")
+    P = n_pairs.value
+    return birth[:P], death[:P], bval[:P], dval[:P], n_roots.value
+
+
+class BatchPlan:
+    """Buffers of one batch configuration (reused across calls, so the library's
+    cached graph for these pointers is replayed)."""
+
+    def __init__(self, shapes: Sequence[Sequence[int]], device, pair_capacity: int | None = None):
+        lib = load_library()
+        self.shapes = [tuple(int(s) for s in shp) for shp in shapes]
+        self.dims = [grid_dims(s) for s in self.shapes]
+        self.sizes = [nx * ny * nz for nx, ny, nz in self.dims]
+        self.n_total = sum(self.sizes)
+        self.device = torch.device(device)
+        self._dims_c = (ctypes.c_int64 * (3 * len(self.dims)))(*[v for d in self.dims for v in d])
+        ws = lib.mt_batch_workspace_bytes(self._dims_c, len(self.dims))
+        if ws == 0:
+            raise MTError(-1, "mt_batch_workspace_bytes")
+        if pair_capacity is None:
+            pair_capacity = sum(n // 2 + 1 for n in self.sizes)
+        self.pair_capacity = int(pair_capacity)
+        dev = self.device
+        self.fields = torch.empty(self.n_total, dtype=torch.float32, device=dev)
+        self.triplets = torch.empty((self.n_total, 2), dtype=torch.int32, device=dev)
+        cap = max(self.pair_capacity, 1)
+        self.birth = torch.empty(cap, dtype=torch.int32, device=dev)
+        self.death = torch.empty(cap, dtype=torch.int32, device=dev)
+        self.bval = torch.empty(cap, dtype=torch.float32, device=dev)
+        self.dval = torch.empty(cap, dtype=torch.float32, device=dev)
+        self.pair_offsets = torch.empty(len(self.dims) + 1, dtype=torch.int64, device=dev)
+        self.workspace = alloc_workspace(ws, dev)
+        starts = [0]
+        for n in self.sizes:
+            starts.append(starts[-1] + n)
+        self.vertex_offsets = starts
+
+    def load(self, fields: Sequence[torch.Tensor]):
+        for i, f in enumerate(fields):
+            a, b = self.vertex_offsets[i], self.vertex_offsets[i + 1]
+            self.fields[a:b].copy_(f.reshape(-1))
+
+    def launch(self):
+        rc = load_library().mt_batch_build(
+            self.fields.data_ptr(), self._dims_c, len(self.dims), self.triplets.data_ptr(), self.birth.data_ptr(),
+            self.death.data_ptr(), self.bval.data_ptr(), self.dval.data_ptr(), self.pair_capacity,
+            self.pair_offsets.data_ptr(), self.workspace.data_ptr(), self.workspace.numel(),
+            _stream_ptr(self.device))
+        _check(rc, "mt_batch_build")
+
+    def sync_status(self):
+        n_pairs = ctypes.c_int64(0)
+        rc = load_library().mt_sync_status(self.workspace.data_ptr(), _stream_ptr(self.device),
+                                           ctypes.byref(n_pairs), None)
+        _check(rc, "mt_batch_build (device status)")
+        return n_pairs.value
+
+    def backward(self, grad_birth: torch.Tensor, grad_death: torch.Tensor, grad_field: torch.Tensor | None = None,
+                 accumulate: bool = False) -> torch.Tensor:
+        if grad_field is None:
+            grad_field = torch.empty(self.n_total, dtype=torch.float32, device=self.device)
+        return mt_pairs_backward(self._dims_c, len(self.dims), self.pair_offsets, self.pair_capacity, self.birth,
+                                 self.death, grad_birth, grad_death, grad_field, accumulate)
+
+
+def mt_batch_build(fields: Sequence[torch.Tensor], plan: BatchPlan | None = None, sync: bool = True):
+    """Merge trees + pairs of many fields in one graph launch; returns the plan holding the outputs."""
+    if plan is None:
+        plan = BatchPlan([f.shape for f in fields], fields[0].device)
+    plan.load(fields)
+    plan.launch()
+    if sync:
+        plan.sync_status()
+    return plan
+
+
+def mt_pairs_backward(dims_c, n_fields: int, pair_offsets: torch.Tensor, pair_capacity: int, birth: torch.Tensor,
+                      death: torch.Tensor, grad_birth: torch.Tensor, grad_death: torch.Tensor,
+                      grad_field: torch.Tensor, accumulate: bool = False) -> torch.Tensor:
+    """grad_field[birth] += grad_birth; grad_field[death] += grad_death (concatenated batch ids)."""
+    if not isinstance(dims_c, ctypes.Array):
+        flat = [int(v) for d in dims_c for v in d]
+        dims_c = (ctypes.c_int64 * len(flat))(*flat)
+    gb = grad_birth.contiguous()
+    gd = grad_death.contiguous()
+    if gb.dtype != torch.float32 or gd.dtype != torch.float32 or grad_field.dtype != torch.float32:
+        raise TypeError("gradients must be float32")
+    n = min(pair_capacity, gb.numel(), gd.numel(), birth.numel(), death.numel())
+    rc = load_library().mt_pairs_backward(dims_c, n_fields, pair_offsets.data_ptr(), n, birth.data_ptr(),
+                                          death.data_ptr(), gb.data_ptr(), gd.data_ptr(), grad_field.data_ptr(),
+                                          1 if accumulate else 0, _stream_ptr(grad_field.device))
+    _check(rc, "mt_pairs_backward")
+    return grad_field
+
+
+class MergeTreePairs(torch.autograd.Function):
+    """Persistence pairs of a batch of fields as differentiable values.
+
+    forward(flat_fields, plan) -> (birth_val, death_val) over all pairs of all
+    fields (concatenated; ``plan.pair_offsets`` splits them per field).  The
+    pairing is piecewise constant in the field, so the derivative of a birth
+    value is 1 at its birth vertex and that of a death value 1 at its death
+    vertex; backward scatters the upstream gradients there with the library's
+    adjoint kernel.
+    """
+
+    @staticmethod
+    def forward(ctx, flat_fields: torch.Tensor, plan: BatchPlan):
+        plan.fields.copy_(flat_fields.detach().reshape(-1))
+        plan.launch()
+        P = plan.sync_status()
+        if P > plan.pair_capacity:
+            raise MTError(-4, "MergeTreePairs")
+        ctx.plan = plan
+        ctx.P = P
+        # the plan's buffers are reused by the next forward: keep this pairing
+        ctx.save_for_backward(plan.birth[:P].clone(), plan.death[:P].clone(), plan.pair_offsets.clone())
+        return plan.bval[:P].clone(), plan.dval[:P].clone()
+
+    @staticmethod
+    def backward(ctx, g_birth, g_death):
+        plan, P = ctx.plan, ctx.P
+        dev = plan.device
+        gb = torch.zeros(P, dtype=torch.float32, device=dev) if g_birth is None else g_birth.float()
+        gd = torch.zeros(P, dtype=torch.float32, device=dev) if g_death is None else g_death.float()
+        birth, death, offsets = ctx.saved_tensors
+        grad = torch.empty(plan.n_total, dtype=torch.float32, device=dev)
+        mt_pairs_backward(plan._dims_c, len(plan.dims), offsets, P, birth, death, gb, gd, grad)
+        return grad, None
+
+
+def release_caches():
+    load_library().mt_release_caches()

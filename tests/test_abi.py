@@ -1,0 +1,94 @@
+"""The C-ABI library loads, exports what include/mt.h declares, and rejects bad
+arguments on the host (no GPU work is enqueued by these calls)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mt.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(mt_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2301_10838_amd.mt as mt
+
+    if not os.path.exists(mt.LIB_PATH):
+        from paper_2301_10838_amd import build
+
+        build.build()
+    return mt.load_library()
+
+
+def test_exports_match_header(lib):
+    import paper_2301_10838_amd.mt as mt
+
+    names = _declared()
+    assert names == sorted(mt.EXPORTS)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_status_strings(lib):
+    for code, name in [(0, b"MT_OK"), (-1, b"MT_ERR_INVALID_ARG"), (-3, b"MT_ERR_NAN"), (-8, b"MT_ERR_INTERNAL")]:
+        assert lib.mt_status_string(code) == name
+
+
+def test_workspace_sizes(lib):
+    assert lib.mt_workspace_bytes(0, 1, 1) == 0
+    assert lib.mt_workspace_bytes(1 << 31, 1, 1) == 0
+    assert lib.mt_workspace_bytes(2048, 1024, 1024) == 0  # 2^31 vertices
+    w = lib.mt_workspace_bytes(64, 64, 64)
+    assert w >= 4 * 64 ** 3 and w % 256 == 0
+    dims = (ctypes.c_int64 * 6)(64, 64, 64, 100, 90, 1)
+    wb = lib.mt_batch_workspace_bytes(dims, 2)
+    assert wb >= 4 * (64 ** 3 + 9000)
+    assert lib.mt_batch_workspace_bytes(dims, 0) == 0
+
+
+def test_host_argument_checks(lib):
+    fake = ctypes.c_void_p(0x10000)  # never dereferenced: checks fail first
+    ws = lib.mt_workspace_bytes(8, 8, 8)
+    # bad dims
+    assert lib.mt_build(fake, 0, 8, 8, fake, fake, ws, None) == -1
+    assert lib.mt_build(fake, -3, 8, 8, fake, fake, ws, None) == -1
+    # too many vertices for 32-bit ids
+    assert lib.mt_build(fake, 1 << 16, 1 << 15, 1, fake, fake, ws, None) == -2
+    # null / misaligned triplets
+    assert lib.mt_build(fake, 8, 8, 8, None, fake, ws, None) == -1
+    assert lib.mt_build(fake, 8, 8, 8, ctypes.c_void_p(0x10004), fake, ws, None) == -1
+    # workspace missing, misaligned or too small
+    assert lib.mt_build(fake, 8, 8, 8, fake, None, ws, None) == -6
+    assert lib.mt_build(fake, 8, 8, 8, fake, ctypes.c_void_p(0x10010), ws, None) == -6
+    assert lib.mt_build(fake, 8, 8, 8, fake, fake, ws - 1, None) == -6
+    # pairs: n_pairs required, negative capacity
+    n = ctypes.c_int64(0)
+    assert lib.mt_persistence_pairs(fake, fake, 8, 8, 8, fake, fake, fake, fake, 10, None, None, fake, ws,
+                                    None) == -1
+    assert lib.mt_persistence_pairs(fake, fake, 8, 8, 8, fake, fake, fake, fake, -1, ctypes.byref(n), None,
+                                    fake, ws, None) == -1
+    # batch: no fields, bad dims
+    dims = (ctypes.c_int64 * 3)(8, 0, 8)
+    assert lib.mt_batch_build(fake, dims, 1, fake, fake, fake, fake, fake, 10, fake, fake, 1 << 20, None) == -1
+    assert lib.mt_batch_build(fake, dims, 0, fake, fake, fake, fake, fake, 10, fake, fake, 1 << 20, None) == -1
+    big = (ctypes.c_int64 * 6)(1 << 15, 1 << 15, 1, 1 << 15, 1 << 15, 1)
+    assert lib.mt_batch_build(fake, big, 2, fake, fake, fake, fake, fake, 10, fake, fake, 1 << 20, None) == -2
+    # backward
+    assert lib.mt_pairs_backward(dims, 1, fake, 0, None, None, None, None, fake, 0, None) == -1
+    assert lib.mt_sync_status(None, None, None, None) == -6
+
+
+def test_binding_refuses_cpu_tensors():
+    import torch
+
+    import paper_2301_10838_amd.mt as mt
+
+    with pytest.raises(TypeError):
+        mt.mt_build(torch.zeros(4, 4))
