@@ -1,0 +1,338 @@
+"""Benchmark of the triplet merge tree path on one MI355X.
+
+One step = the whole single-field hot path on the 512^3 log-normal k^-3 field
+(merge tree with mt_build, then persistence pairs with mt_persistence_pairs,
+which synchronizes to return the pair count), with the field already resident
+in HBM.  Prints one JSON line.
+
+Also reported (under "secondary"): the uneven 48-field batch in one graph
+launch against 48 plain calls, and the backward scatter of a 16 x 128^3
+differentiable batch.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import hashlib
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+SRC = os.path.join(ROOT, "paper_2301_10838_amd", "csrc", "mt.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+# Compulsory HBM bytes each kernel must move, per vertex of its launch (plus
+# the per-minimum and per-pair terms noted in algo_bytes).  "Minima" here are
+# the local minima of the tiles, whose 24-byte records (16-byte slot + 8-byte
+# key) the kernels pass on to each other.
+ALGO_BYTES_PER_VERTEX = {
+    "k_local": 8,        # read f, write the local-basin label
+    "k_cross": 0,        # face edges only (per-minimum term below)
+    "k_repair_min": 0,   # per-minimum term below
+    "k_repair_reg": 16,  # read label and f, write the triplet
+    "k_pairs_count": 8,  # read the triplet
+    "k_pairs_write": 8,  # read the triplet (+16 per pair written)
+}
+
+
+def algo_bytes(kernel: str, n_vertices: int, n_pairs: int, n_local_minima: int) -> float:
+    b = ALGO_BYTES_PER_VERTEX[kernel] * n_vertices
+    if kernel == "k_local":
+        b += 24 * n_local_minima   # write slot + key of every local minimum
+    if kernel in ("k_cross", "k_repair_min"):
+        b += 16 * n_local_minima   # read (and rewrite) every slot once
+    if kernel == "k_pairs_write":
+        b += 16 * n_pairs          # birth, death ids and values
+    return float(b)
+
+
+def src_hash() -> str:
+    with open(SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()
+
+
+def stored_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("src_sha256") != src_hash() or t.get("workload") != workload:
+        return None
+    k = t.get("kernels", {}).get(kernel)
+    if not k:
+        return None
+    return float(k["fetch_bytes"] + k["write_bytes"])
+
+
+class Single:
+    """Preallocated buffers for repeated single-field calls through the C ABI."""
+
+    def __init__(self, ft, lib, mt):
+        import torch
+
+        self.lib, self.mt = lib, mt
+        self.ft = ft
+        self.dims = mt.grid_dims(ft.shape)
+        nx, ny, nz = self.dims
+        self.N = nx * ny * nz
+        dev = ft.device
+        self.T = torch.empty((self.N, 2), dtype=torch.int32, device=dev)
+        self.ws = mt.alloc_workspace(lib.mt_workspace_bytes(nx, ny, nz), dev)
+        self.cap = self.N // 2 + 1
+        self.b = torch.empty(self.cap, dtype=torch.int32, device=dev)
+        self.d = torch.empty(self.cap, dtype=torch.int32, device=dev)
+        self.bv = torch.empty(self.cap, dtype=torch.float32, device=dev)
+        self.dv = torch.empty(self.cap, dtype=torch.float32, device=dev)
+        self.np = ctypes.c_int64(0)
+        self.nr = ctypes.c_int64(0)
+        self.stream = torch.cuda.current_stream(dev).cuda_stream
+
+    def step(self):
+        nx, ny, nz = self.dims
+        rc = self.lib.mt_build(self.ft.data_ptr(), nx, ny, nz, self.T.data_ptr(), self.ws.data_ptr(),
+                               self.ws.numel(), self.stream)
+        if rc != 0:
+            raise self.mt.MTError(rc, "mt_build")
+        rc = self.lib.mt_persistence_pairs(self.ft.data_ptr(), self.T.data_ptr(), nx, ny, nz, self.b.data_ptr(),
+                                           self.d.data_ptr(), self.bv.data_ptr(), self.dv.data_ptr(), self.cap,
+                                           ctypes.byref(self.np), ctypes.byref(self.nr), self.ws.data_ptr(),
+                                           self.ws.numel(), self.stream)
+        if rc != 0:
+            raise self.mt.MTError(rc, "mt_persistence_pairs")
+        return self.np.value, self.nr.value
+
+
+def cpu_baseline(f: np.ndarray, dev, mt, lib):
+    """Oracle (serial, one core) on a bounded slab of the workload, and the GPU
+    on the same slab, checked bit for bit."""
+    import torch
+
+    import oracle
+
+    nz = f.shape[0]
+    slab_z = 64 if f.ndim == 3 and nz > 64 else nz
+    sample = np.ascontiguousarray(f[:slab_z])
+    t0 = time.perf_counter()
+    T_ref = oracle.merge_tree(sample)
+    rb, rd, _, _, _ = oracle.pairs(sample, T_ref)
+    dt = time.perf_counter() - t0
+    s = Single(torch.from_numpy(sample).to(dev), lib, mt)
+    P, _ = s.step()
+    torch.cuda.synchronize()
+    exact = bool(np.array_equal(s.T.cpu().numpy().view(np.uint32), T_ref)
+                 and np.array_equal(s.b[:P].cpu().numpy().view(np.uint32), rb)
+                 and np.array_equal(s.d[:P].cpu().numpy().view(np.uint32), rd))
+    return {
+        "value": sample.size / dt / 1e6,
+        "unit": "Mvertices/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"z < {slab_z} slab {list(sample.shape)} ({sample.size} vertices) of the timed field; "
+                  f"serial sort + union-find sweep + pairs, {dt:.1f} s",
+        "host_cores_available": os.cpu_count(),
+        "gpu_bit_exact_on_sample": exact,
+    }
+
+
+def bench_batch(dev, mt, lib, reps: int = 5):
+    import torch
+
+    from paper_2301_10838_amd import fields
+
+    fs = fields.workload("batch48")
+    shapes = [f.shape for f in fs]
+    plan = mt.BatchPlan(shapes, dev)
+    plan.load([torch.from_numpy(f).to(dev) for f in fs])
+    n_total = plan.n_total
+    for _ in range(2):
+        plan.launch()
+        plan.sync_status()
+    torch.cuda.synchronize()
+    tb = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        plan.launch()
+        P = plan.sync_status()
+        tb.append(time.perf_counter() - t0)
+    # plain: one mt_build + mt_persistence_pairs per field
+    singles = [Single(plan.fields[plan.vertex_offsets[i]:plan.vertex_offsets[i + 1]].view(shapes[i]), lib, mt)
+               for i in range(len(shapes))]
+    for s in singles:
+        s.step()
+    torch.cuda.synchronize()
+    tp = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        for s in singles:
+            s.step()
+        torch.cuda.synchronize()
+        tp.append(time.perf_counter() - t0)
+    # identical results, field by field
+    offs = plan.pair_offsets.cpu().numpy()
+    T_all = plan.triplets.cpu().numpy().view(np.uint32)
+    b_all = plan.birth.cpu().numpy().view(np.uint32)
+    same = True
+    for i, s in enumerate(singles):
+        a, b = plan.vertex_offsets[i], plan.vertex_offsets[i + 1]
+        p = s.np.value
+        same &= bool(np.array_equal(T_all[a:b], s.T.cpu().numpy().view(np.uint32)))
+        same &= bool(offs[i + 1] - offs[i] == p)
+        same &= bool(np.array_equal(b_all[offs[i]:offs[i + 1]], s.b[:p].cpu().numpy().view(np.uint32)))
+    tb_med, tp_med = statistics.median(tb), statistics.median(tp)
+    return {
+        "workload": "batch48",
+        "fields": len(shapes),
+        "vertices": n_total,
+        "pairs": int(P),
+        "batched_ms": tb_med * 1e3,
+        "plain_ms": tp_med * 1e3,
+        "batched_Mvertices_per_s": n_total / tb_med / 1e6,
+        "plain_Mvertices_per_s": n_total / tp_med / 1e6,
+        "batched_over_plain": tp_med / tb_med,
+        "batched_equals_plain": same,
+    }
+
+
+def bench_backward(dev, mt, steps: int = 20):
+    import torch
+
+    from paper_2301_10838_amd import fields
+
+    fs = fields.workload("diff16x128")
+    plan = mt.BatchPlan([f.shape for f in fs], dev)
+    flat = torch.cat([torch.from_numpy(f).to(dev).reshape(-1) for f in fs])
+    tau, lr = 0.05, 0.1
+    bwd_us, fwd_ms, losses = [], [], []
+    mt.profile_begin()
+    for it in range(steps):
+        x = flat.clone().requires_grad_(True)
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record()
+        births, deaths = mt.MergeTreePairs.apply(x, plan)
+        pers = deaths - births
+        loss = torch.where(pers < tau, pers * pers, torch.zeros_like(pers)).sum()
+        e1.record()
+        loss.backward()
+        e2.record()
+        torch.cuda.synchronize()
+        fwd_ms.append(e0.elapsed_time(e1))
+        bwd_us.append(e1.elapsed_time(e2) * 1e3)
+        losses.append(float(loss))
+        with torch.no_grad():
+            flat -= lr * x.grad
+    ks = mt.profile_end()
+    kern_ms = sum(ks.get(k, (0.0, 0))[0] for k in ("k_fill0", "k_scatter"))
+    return {
+        "workload": "diff16x128",
+        "vertices": plan.n_total,
+        "steps": steps,
+        "bwd_kernel_us": kern_ms / steps * 1e3,
+        "bwd_us_median": statistics.median(bwd_us[2:]),
+        "fwd_ms_median": statistics.median(fwd_ms[2:]),
+        "loss_first": losses[0],
+        "loss_last": losses[-1],
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="grf512")
+    ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: the merge-tree path here runs on a single MI355X and has no "
+              "multi-GPU mode; run it with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2301_10838_amd.mt as mt
+    from paper_2301_10838_amd import fields
+
+    lib = mt.load_library()
+    dev = torch.device("cuda:0")
+    f = fields.workload(args.workload)[0]
+    ft = torch.from_numpy(f).to(dev)
+    s = Single(ft, lib, mt)
+    for _ in range(args.warmup):
+        s.step()
+    torch.cuda.synchronize()
+
+    mt.profile_begin()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        P, R = s.step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kstats = mt.profile_end()
+    dt = (t1 - t0) / args.steps
+    N = s.N
+
+    n_min = mt.build_stats(s.ws)  # local minima records of the build
+    dom = max((k for k in kstats if k in ALGO_BYTES_PER_VERTEX), key=lambda k: kstats[k][0])
+    avg_s = kstats[dom][0] / kstats[dom][1] / 1e3
+    ab = algo_bytes(dom, N, P, n_min)
+    achieved = ab / avg_s / 1e9
+    traffic = stored_traffic(dom, args.workload)
+    roofline = {
+        "bound": "hbm",
+        "achieved": achieved,
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": achieved / HBM_PEAK_GBS,
+        "traffic": traffic,
+        "kernel": dom,
+        "kernel_avg_ms": avg_s * 1e3,
+        "algo_bytes_per_launch": ab,
+    }
+    per_kernel = {k: {"avg_ms": v[0] / v[1], "launches": v[1]} for k, v in sorted(kstats.items())}
+    path_bytes = sum(algo_bytes(k, N, P, n_min) for k in ALGO_BYTES_PER_VERTEX)
+
+    out = {
+        "metric": "Mvertices/s merge tree+pairs (bit-exact), batched vs plain; %HBM peak; bwd μs",
+        "value": N / dt / 1e6,
+        "unit": "Mvertices/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "shape": list(f.shape), "vertices": N, "connectivity": 6,
+                   "pairs": P, "roots": R, "tile_local_minima": n_min},
+        "roofline": roofline,
+        "path_algo_GBps": path_bytes / dt / 1e9,
+        "kernels": per_kernel,
+    }
+    if not args.no_secondary:
+        out["secondary"] = {"batched": bench_batch(dev, mt, lib), "backward": bench_backward(dev, mt)}
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(f, dev, mt, lib)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -157,6 +157,13 @@ int mt_batch_build(const float *fields, const int64_t *dims, int32_t n_fields,
 int mt_sync_status(const void *workspace, void *stream, int64_t *n_pairs, int64_t *n_roots);
 
 /*
+ * mt_build_stats -- synchronize `stream` and report, for the last build on
+ * `workspace`, the number of tile-local minima the build kept a merge record
+ * for (an internal size, reported for measurement).
+ */
+int mt_build_stats(const void *workspace, void *stream, int64_t *n_local_minima);
+
+/*
  * mt_pairs_backward -- adjoint of the pair readout.  A pair's birth value is
  * f at its birth vertex and its death value is f at its death vertex, so for
  * upstream gradients gb, gd:  grad[birth_k] += gb_k,  grad[death_k] += gd_k.
@@ -176,6 +183,20 @@ int mt_pairs_backward(const int64_t *dims, int32_t n_fields, const int64_t *pair
                       int64_t pair_capacity, const uint32_t *birth, const uint32_t *death,
                       const float *grad_birth, const float *grad_death, float *grad_field,
                       int accumulate, void *stream);
+
+/*
+ * Per-kernel timing with HIP events, for measurement.  mt_profile_begin
+ * clears the counters and turns timing on: every kernel the library launches
+ * afterwards (outside graph capture) is bracketed by two events on its launch
+ * stream.  mt_profile_end waits for those events, accumulates the elapsed
+ * time per kernel name and turns timing off.  mt_profile_get(i, ...) returns
+ * the i-th kernel name (copied into name[name_len]), its summed time in ms
+ * and its launch count; i runs over [0, mt_profile_count()).
+ */
+int mt_profile_begin(void);
+int mt_profile_end(void);
+int mt_profile_count(void);
+int mt_profile_get(int i, char *name, size_t name_len, double *total_ms, int64_t *launches);
 
 /* Free cached graph plans (device and host memory they hold).  Not safe to
  * call while another thread is inside the library. */

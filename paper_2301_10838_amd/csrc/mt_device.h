@@ -1,0 +1,799 @@
+// mt_device.h -- device code of the triplet merge tree library (gfx950).
+//
+// Included once, by mt.hip.  The method is the triplet merge tree of "Fast
+// Merge Tree Computation via SYCL" (arXiv 2301.10838): Sec. 2, Alg. 1-5, with
+// the GPU layout of Sec. 3.2 (a triplet (u, s, v) is stored as T[u] = (s, v),
+// two 32-bit ids packed into one 64-bit word, so one 64-bit compare-and-swap
+// replaces it atomically).
+//
+// Pipeline of one build (every field of a batch at once):
+//
+//   k_local<S>      one workgroup per tile, everything in LDS: the merge tree
+//                   of the tile's own subgraph.  Each vertex points at its
+//                   lowest lower neighbour inside the tile, chains are
+//                   followed to the tile-local minimum, every edge inside the
+//                   tile joining two different local basins is merged
+//                   (Alg. 3 with LDS compare-and-swap) and the local minima
+//                   are repaired (Alg. 5).  The tile's local minima get
+//                   consecutive "minimum numbers"; their triplets go to the
+//                   global minima array and every vertex records the number
+//                   of its local basin.
+//   k_cross<S>      one workgroup per tile: Merge (Alg. 3 with 64-bit
+//                   compare-and-swap in global memory) of every edge that
+//                   leaves the tile through its +x, +y, +z faces, between the
+//                   local minima of its two ends.
+//   k_repair_min    Repair of every local minimum.
+//   k_repair_reg    every vertex's output triplet: a local minimum copies its
+//                   own, any other vertex u gets (u, u, representative of its
+//                   local minimum at the level of u); pair counts per chunk.
+//   k_pairs_*       pairs read out of T in ascending birth id.
+//
+// Why this computes the paper's tree.  Alg. 1 merges the edges in any order,
+// and the triplet representation that is both normalized and minimal is
+// unique (Sec. 2), so every schedule of merges followed by a repair ends in
+// the same T.  (1) Pointing each vertex at its lowest lower neighbour is the
+// state Merge reaches when those edges are merged one by one in decreasing
+// order of their upper vertex.  (2) Following those pointers to the minimum
+// z(u) they reach only shortens links that all lie below u, so (u, u, z(u))
+// represents the same connectivity; an edge whose two ends reach the same
+// minimum then joins vertices already connected below its upper end and needs
+// no merge, and any other edge (a, b) is the fact "z(a) and z(b) are
+// connected at the level of max(a, b)".  (3) Merging the edges inside each
+// tile first (and repairing), then the edges between tiles, is one more
+// schedule of the same merges.  Only minima ever carry a changing triplet.
+//
+// Minimum slots.  Minimum number m owns a 16-byte slot: w = (saddle id,
+// target number) is the triplet, replaced by 64-bit compare-and-swap; k is
+// the 64-bit order key of w's saddle, stored after every successful swap.  A
+// reader uses k only if its id part matches the saddle it read in w, and
+// otherwise reads the saddle's value from the field, so a stale k costs time,
+// never correctness.  mkey[m] is the key of the minimum itself.
+//
+// Order.  Vertices compare by (value, id) with IEEE semantics: the float is
+// mapped to an order-preserving uint32 with -0.0 folded onto +0.0, and the id
+// is appended, so every comparison is one 64-bit integer compare.  Inside a
+// tile the id is replaced by the position in the tile, which orders the same
+// way (both grow with z, then y, then x).
+//
+// Safety.  Every id read back from memory is range-checked before it is used
+// as an address; a failed check latches ST_CORRUPT instead of faulting, and
+// every loop is bounded by a step cap that latches ST_LIVELOCK.
+
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mtd {
+
+constexpr int kBlock = 256;                  // threads per workgroup of the flat passes
+constexpr int kChunk = 4096;                 // vertices per workgroup in flat passes
+constexpr int kSetupMax = 12;                // field descriptors per k_setup launch
+constexpr int kBwdGroup = 64;                // fields per backward launch
+
+constexpr uint32_t ST_NAN = 1u, ST_LIVELOCK = 2u, ST_CAPACITY = 4u, ST_CORRUPT = 8u;
+
+struct FieldDesc {
+    int32_t nx, ny, nz;
+    int32_t ntx, nty, ntz;   // tiles along each axis
+    int32_t tpos;            // position of the field in tile order
+    int32_t pad;
+    int64_t offset;          // global id of the first vertex
+    int64_t n;               // vertices
+    int64_t tile_start;      // first tile (tile order)
+    int64_t chunk_start;     // first chunk (field order)
+};
+
+struct Header {
+    uint32_t status;
+    uint32_t n_minima;       // minimum numbers handed out
+    int64_t total_pairs;
+    int64_t roots;
+    int64_t reserved[5];
+};
+
+struct Slot {
+    uint64_t w;  // (saddle id, target number): the triplet
+    uint64_t k;  // order key of the saddle, valid if its low half equals w's saddle
+};
+
+// ---------------------------------------------------------------------------
+// helpers
+
+__device__ __forceinline__ uint32_t okey(float x)
+{
+    uint32_t b = __float_as_uint(x);
+    b = (b == 0x80000000u) ? 0u : b;  // -0.0 == +0.0
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+
+__device__ __forceinline__ uint64_t vkey(const float *__restrict__ f, uint32_t id)
+{
+    return ((uint64_t)okey(f[id]) << 32) | id;
+}
+
+__device__ __forceinline__ uint32_t lo32(uint64_t t) { return (uint32_t)t; }
+__device__ __forceinline__ uint32_t hi32(uint64_t t) { return (uint32_t)(t >> 32); }
+__device__ __forceinline__ uint64_t pack(uint32_t s, uint32_t v) { return (uint64_t)s | ((uint64_t)v << 32); }
+
+// Untorn 64-bit read/write of a slot word.  The merge phase reads through the
+// cache: a stale triplet is a fact that held earlier and still holds, and
+// the compare-and-swap, which always sees the current word, hands back the
+// fresh value when the read was stale.
+template <typename T>
+__device__ __forceinline__ T ld_relaxed(T *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+template <typename T>
+__device__ __forceinline__ void st_relaxed(T *p, T v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+
+// Key of the saddle s of slot x: the cached key if it belongs to s.
+__device__ __forceinline__ uint64_t saddle_key(Slot *__restrict__ S, const float *__restrict__ f, uint32_t x,
+                                               uint32_t s)
+{
+    const uint64_t k = ld_relaxed(&S[x].k);
+    return lo32(k) == s ? k : vkey(f, s);
+}
+
+template <typename I>
+__device__ __forceinline__ int search(const I *__restrict__ starts, int nf, int64_t t)
+{
+    int lo = 0, hi = nf;  // starts[lo] <= t < starts[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if ((int64_t)starts[mid] <= t) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// Workgroups are dealt round-robin to the 8 XCDs; give each XCD a contiguous
+// run of tiles so that neighbouring tiles (which share halo lines) share an L2.
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t G, int remap)
+{
+    if (!remap || G < 8) return b;
+    const int64_t per = G / 8, rem = G % 8;
+    const int64_t x = b % 8, j = b / 8;
+    return x * per + (x < rem ? x : rem) + j;
+}
+
+__device__ __forceinline__ uint64_t lanemask_lt()
+{
+    const int lane = threadIdx.x & 63;
+    return lane ? (~0ull >> (64 - lane)) : 0ull;
+}
+
+// Tile shape and workgroup size.
+template <int X, int Y, int Z, int NTHREADS>
+struct Shape {
+    static constexpr int TX = X, TY = Y, TZ = Z, VOL = X * Y * Z, NT = NTHREADS;
+    static_assert(VOL % NT == 0 && NT % 64 == 0 && VOL <= 4096, "tile volume");
+    static_assert((X & (X - 1)) == 0 && (Y & (Y - 1)) == 0 && (Z & (Z - 1)) == 0, "powers of two");
+};
+
+struct TileCtx {
+    FieldDesc d;
+    int64_t t;   // global tile index
+    int x0, y0, z0, ex, ey, ez;
+    int64_t sxy;
+};
+
+template <class S>
+__device__ __forceinline__ TileCtx tile_ctx(const FieldDesc *__restrict__ D, const int32_t *__restrict__ tfield,
+                                            const int64_t *__restrict__ tstart, int nfc, int64_t t)
+{
+    TileCtx c;
+    const int k = search(tstart, nfc, t);
+    c.d = D[tfield[k]];
+    c.t = t;
+    const int64_t lt = t - c.d.tile_start;
+    const int bx = (int)(lt % c.d.ntx);
+    const int64_t r = lt / c.d.ntx;
+    const int by = (int)(r % c.d.nty);
+    const int bz = (int)(r / c.d.nty);
+    c.x0 = bx * S::TX; c.y0 = by * S::TY; c.z0 = bz * S::TZ;
+    c.ex = min(S::TX, c.d.nx - c.x0);
+    c.ey = min(S::TY, c.d.ny - c.y0);
+    c.ez = min(S::TZ, c.d.nz - c.z0);
+    c.sxy = (int64_t)c.d.nx * c.d.ny;
+    return c;
+}
+
+// ---------------------------------------------------------------------------
+// setup
+
+struct SetupArgs {
+    FieldDesc d[kSetupMax];
+    int32_t first, count, nf;
+    uint32_t clear_status;  // status bits to clear
+    int32_t zero_counts;
+    int32_t pad;
+    int64_t total_tiles, total_chunks;
+};
+
+__global__ void k_setup(SetupArgs a, FieldDesc *D, int32_t *tfield, int64_t *tstart, int64_t *cs, Header *h)
+{
+    const int i = threadIdx.x;
+    if (i < a.count) {
+        const FieldDesc d = a.d[i];
+        D[a.first + i] = d;
+        tfield[d.tpos] = a.first + i;
+        tstart[d.tpos] = d.tile_start;
+        cs[a.first + i] = d.chunk_start;
+    }
+    if (i == 0) {
+        if (a.first + a.count == a.nf) {
+            tstart[a.nf] = a.total_tiles;
+            cs[a.nf] = a.total_chunks;
+        }
+        if (a.clear_status) h->status &= ~a.clear_status;
+        if (a.zero_counts) {
+            h->total_pairs = 0;
+            h->roots = 0;
+            h->n_minima = 0;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 1. merge tree of each tile's subgraph, in LDS
+
+// LDS triplet of local minimum i: low 16 bits = saddle (position in the tile),
+// high 16 bits = target (local minimum index).
+__device__ __forceinline__ uint64_t tkey(const uint32_t *hk, uint32_t p) { return ((uint64_t)hk[p] << 32) | p; }
+
+__device__ __forceinline__ uint32_t lds_ld(uint32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Merge (Alg. 3) of "local minima u and v are connected at level s" (s a tile
+// position).  Descents stop at roots; after a swap that replaced a root
+// nothing was displaced; otherwise the displaced triplet is merged again from
+// the lower minimum; a lost swap restarts with the value it saw.
+template <int VOL>
+__device__ void lds_merge(uint32_t *TL, const uint32_t *hk, const uint16_t *mh, uint32_t u, uint32_t s,
+                          uint32_t v, uint32_t cap, uint32_t &err)
+{
+    uint64_t ks = tkey(hk, s);
+    uint32_t tu = lds_ld(TL + u), tv = lds_ld(TL + v);
+    for (uint32_t step = 0; step < cap; ++step) {
+        const uint32_t u1 = tu >> 16, su = tu & 0xffffu, v1 = tv >> 16, sv = tv & 0xffffu;
+        if (u1 >= (uint32_t)VOL || v1 >= (uint32_t)VOL) { err |= ST_CORRUPT; return; }
+        if (u1 != u && tkey(hk, su) < ks) { u = u1; tu = lds_ld(TL + u); continue; }
+        if (v1 != v && tkey(hk, sv) < ks) { v = v1; tv = lds_ld(TL + v); continue; }
+        if (u == v) return;
+        if (tkey(hk, mh[v]) < tkey(hk, mh[u])) {
+            const uint32_t w = u; u = v; v = w;
+            const uint32_t tw = tu; tu = tv; tv = tw;
+        }
+        uint32_t seen = tv;
+        if (__hip_atomic_compare_exchange_strong(TL + v, &seen, s | (u << 16), __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_WORKGROUP)) {
+            if ((tv >> 16) == v) return;
+            s = tv & 0xffffu;
+            ks = tkey(hk, s);
+            v = tv >> 16;
+            tv = lds_ld(TL + v);
+        } else {
+            tv = seen;
+        }
+        tu = lds_ld(TL + u);
+    }
+    err |= ST_LIVELOCK;
+}
+
+template <class S>
+__global__ __launch_bounds__(S::NT) void k_local(const float *__restrict__ f, uint32_t *__restrict__ lbl,
+                                                 Slot *__restrict__ slot, uint64_t *__restrict__ mkey,
+                                                 const FieldDesc *__restrict__ D, const int32_t *__restrict__ tfield,
+                                                 const int64_t *__restrict__ tstart, int nfc, int64_t tile0,
+                                                 int64_t ntiles, int remap, uint32_t mcap, uint32_t cap,
+                                                 Header *__restrict__ h)
+{
+    constexpr int NT = S::NT, VOL = S::VOL, TX = S::TX, TY = S::TY;
+    static_assert(VOL <= 65536, "positions fit 16 bits");
+    __shared__ uint32_t hk[VOL];    // order key of every tile vertex
+    __shared__ int16_t wl[VOL];     // lowest lower neighbour in the tile (self at a local minimum)
+    __shared__ uint16_t zl[VOL];    // local minimum index of the vertex's local basin
+    __shared__ uint32_t TL[VOL];    // triplets of the local minima
+    __shared__ uint16_t mh[VOL];    // tile position of local minimum i
+    __shared__ uint32_t wsum[NT / 64];
+    __shared__ uint32_t sb0;
+
+    const int64_t tl = xcd_tile(blockIdx.x, gridDim.x, remap);
+    if (tl >= ntiles) return;
+    const TileCtx c = tile_ctx<S>(D, tfield, tstart, nfc, tile0 + tl);
+    const uint32_t off = (uint32_t)c.d.offset;
+    const float *__restrict__ fb = f + off;
+    auto valid = [&](int lx, int ly, int lz) { return lx < c.ex && ly < c.ey && lz < c.ez; };
+    auto gid = [&](int p) {
+        const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
+        return off + (uint32_t)((c.x0 + lx) + (int64_t)c.d.nx * (c.y0 + ly) + c.sxy * (c.z0 + lz));
+    };
+
+    bool nan = false;
+    for (int p = threadIdx.x; p < VOL; p += NT) {
+        const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
+        uint32_t k = 0xffffffffu;
+        if (valid(lx, ly, lz)) {
+            const float v = fb[(c.x0 + lx) + (int64_t)c.d.nx * (c.y0 + ly) + c.sxy * (c.z0 + lz)];
+            nan |= (v != v);
+            k = okey(v);
+        }
+        hk[p] = k;
+    }
+    if (__ballot(nan) != 0ull && (threadIdx.x & 63) == 0) atomicOr(&h->status, ST_NAN);
+    __syncthreads();
+
+    // lowest lower neighbour inside the tile
+    for (int p = threadIdx.x; p < VOL; p += NT) {
+        const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
+        if (!valid(lx, ly, lz)) continue;
+        uint64_t best = tkey(hk, p);
+        int bp = p;
+#define MT_CAND(cond, q)                                                                    \
+        if (cond) {                                                                         \
+            const uint64_t k = tkey(hk, (q));                                               \
+            if (k < best) { best = k; bp = (q); }                                          \
+        }
+        MT_CAND(lx > 0, p - 1)
+        MT_CAND(lx + 1 < c.ex, p + 1)
+        MT_CAND(ly > 0, p - TX)
+        MT_CAND(ly + 1 < c.ey, p + TX)
+        MT_CAND(lz > 0, p - TX * TY)
+        MT_CAND(lz + 1 < c.ez, p + TX * TY)
+#undef MT_CAND
+        wl[p] = (int16_t)bp;
+    }
+    __syncthreads();
+
+    // number the local minima in tile order; root triplets
+    uint32_t run = 0;
+    const int wave = threadIdx.x >> 6;
+    for (int r0 = 0; r0 < VOL; r0 += NT) {
+        const int p = r0 + threadIdx.x;
+        const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
+        const bool is_min = valid(lx, ly, lz) && wl[p] == p;
+        const uint64_t m = __ballot(is_min);
+        if ((threadIdx.x & 63) == 0) wsum[wave] = (uint32_t)__popcll(m);
+        __syncthreads();
+        uint32_t wb = 0, tot = 0;
+        for (int w = 0; w < NT / 64; ++w) {
+            wb += (w < wave) ? wsum[w] : 0u;
+            tot += wsum[w];
+        }
+        if (is_min) {
+            const uint32_t r = run + wb + (uint32_t)__popcll(m & lanemask_lt());
+            zl[p] = (uint16_t)r;
+            mh[r] = (uint16_t)p;
+            TL[r] = (uint32_t)p | (r << 16);
+        }
+        run += tot;
+        __syncthreads();
+    }
+    const uint32_t cnt = run;
+    if (threadIdx.x == 0) sb0 = atomicAdd(&h->n_minima, cnt);
+
+    // local basins: follow the pointers to the local minimum (keys fall
+    // strictly along them, so at most VOL steps)
+    for (int p = threadIdx.x; p < VOL; p += NT) {
+        const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
+        if (!valid(lx, ly, lz) || wl[p] == p) continue;
+        int x = p;
+        for (int step = 0; step < VOL; ++step) {
+            const int y = wl[x];
+            if (y == x) break;
+            x = y;
+        }
+        zl[p] = zl[x];
+    }
+    __syncthreads();
+    const uint32_t b0 = sb0;
+    if (b0 + cnt > mcap || b0 + cnt < b0) {  // cannot happen: capacity bounds the minima
+        if (threadIdx.x == 0) atomicOr(&h->status, ST_CORRUPT);
+        return;
+    }
+
+    // merge every edge inside the tile whose ends lie in different local basins
+    uint32_t err = 0;
+    for (int p = threadIdx.x; p < VOL; p += NT) {
+        const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
+        if (!valid(lx, ly, lz)) continue;
+        const uint32_t za = zl[p];
+        const uint64_t ka = tkey(hk, p);
+#define MT_EDGE(cond, q)                                                                    \
+        if (cond) {                                                                         \
+            const uint32_t zb = zl[(q)];                                                   \
+            if (zb != za) lds_merge<VOL>(TL, hk, mh, za, tkey(hk, (q)) < ka ? p : (q), zb, cap, err); \
+        }
+        MT_EDGE(lx + 1 < c.ex, p + 1)
+        MT_EDGE(ly + 1 < c.ey, p + TX)
+        MT_EDGE(lz + 1 < c.ez, p + TX * TY)
+#undef MT_EDGE
+    }
+    __syncthreads();
+
+    // Repair (Alg. 5) of the local minima: target -> deepest local minimum
+    // reached through links whose saddle is at or below the minimum's own.
+    for (uint32_t i = threadIdx.x; i < cnt; i += NT) {
+        const uint32_t t = lds_ld(TL + i);
+        const uint32_t s = t & 0xffffu;
+        uint32_t x = t >> 16;
+        if (x == i) continue;
+        const uint64_t ks = tkey(hk, s);
+        for (uint32_t step = 0; step < cap; ++step) {
+            const uint32_t tx = lds_ld(TL + x);
+            const uint32_t v = tx >> 16;
+            if (v >= cnt) { err |= ST_CORRUPT; break; }
+            if (v == x || tkey(hk, tx & 0xffffu) > ks) break;
+            x = v;
+        }
+        if (x != (t >> 16)) __hip_atomic_store(TL + i, s | (x << 16), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+    __syncthreads();
+
+    for (uint32_t i = threadIdx.x; i < cnt; i += NT) {
+        const uint32_t t = TL[i];
+        const uint32_t sp = t & 0xffffu, mp = mh[i];
+        const uint32_t sg = gid((int)sp);
+        slot[b0 + i].w = pack(sg, b0 + (t >> 16));
+        slot[b0 + i].k = ((uint64_t)hk[sp] << 32) | sg;
+        mkey[b0 + i] = ((uint64_t)hk[mp] << 32) | gid((int)mp);
+    }
+    for (int p = threadIdx.x; p < VOL; p += NT) {
+        const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
+        if (valid(lx, ly, lz)) lbl[gid(p)] = b0 + zl[p];
+    }
+    if (err) atomicOr(&h->status, err);
+}
+
+// ---------------------------------------------------------------------------
+// 2. Merge (Alg. 3) across tiles, on the minimum slots
+
+__device__ void gmerge(Slot *__restrict__ S, const uint64_t *__restrict__ mkey, const float *__restrict__ f,
+                       uint32_t M, uint32_t n, uint32_t u, uint32_t s, uint64_t ks, uint32_t v, uint32_t cap,
+                       uint32_t &err)
+{
+    uint64_t tu = ld_relaxed(&S[u].w);
+    uint64_t tv = ld_relaxed(&S[v].w);
+    for (uint32_t step = 0; step < cap; ++step) {
+        const uint32_t u1 = hi32(tu), su = lo32(tu), v1 = hi32(tv), sv = lo32(tv);
+        if (u1 >= M || v1 >= M || su >= n || sv >= n) { err |= ST_CORRUPT; return; }
+        if (u1 != u && saddle_key(S, f, u, su) < ks) { u = u1; tu = ld_relaxed(&S[u].w); continue; }
+        uint64_t kv = 0;
+        if (v1 != v) {
+            kv = saddle_key(S, f, v, sv);
+            if (kv < ks) { v = v1; tv = ld_relaxed(&S[v].w); continue; }
+        }
+        if (u == v) return;
+        if (mkey[v] < mkey[u]) {  // the upper minimum is re-pointed
+            const uint32_t w = u; u = v; v = w;
+            const uint64_t tw = tu; tu = tv; tv = tw;
+            const uint32_t s1 = lo32(tv);
+            kv = (hi32(tv) != v) ? saddle_key(S, f, v, s1) : 0;
+        }
+        uint64_t seen = tv;
+        if (__hip_atomic_compare_exchange_strong(&S[v].w, &seen, pack(s, u), __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT)) {
+            st_relaxed(&S[v].k, ks);
+            if (hi32(tv) == v) return;  // v was a root
+            s = lo32(tv);               // merge the displaced triplet again
+            ks = kv;
+            v = hi32(tv);
+            tv = ld_relaxed(&S[v].w);
+        } else {
+            tv = seen;
+        }
+        tu = ld_relaxed(&S[u].w);
+    }
+    err |= ST_LIVELOCK;
+}
+
+template <class S>
+__global__ __launch_bounds__(S::NT) void k_cross(const float *__restrict__ f, const uint32_t *__restrict__ lbl,
+                                                 Slot *__restrict__ slot, const uint64_t *__restrict__ mkey,
+                                                 const FieldDesc *__restrict__ D, const int32_t *__restrict__ tfield,
+                                                 const int64_t *__restrict__ tstart, int nfc, int64_t tile0,
+                                                 int64_t ntiles, int remap, uint32_t n, uint32_t cap,
+                                                 Header *__restrict__ h)
+{
+    constexpr int TX = S::TX, TY = S::TY, TZ = S::TZ;
+    constexpr int FX = TY * TZ, FY = TX * TZ, FZ = TX * TY;
+    const int64_t tl = xcd_tile(blockIdx.x, gridDim.x, remap);
+    if (tl >= ntiles) return;
+    const TileCtx c = tile_ctx<S>(D, tfield, tstart, nfc, tile0 + tl);
+    const uint32_t off = (uint32_t)c.d.offset;
+    const bool hx = c.x0 + TX < c.d.nx, hy = c.y0 + TY < c.d.ny, hz = c.z0 + TZ < c.d.nz;
+    const uint32_t M = h->n_minima;
+    uint32_t err = 0;
+    for (int e = threadIdx.x; e < FX + FY + FZ; e += S::NT) {
+        int lx, ly, lz;
+        int64_t step;
+        bool ok;
+        if (e < FX) {
+            ly = e % TY; lz = e / TY; lx = TX - 1; step = 1; ok = hx;
+        } else if (e < FX + FY) {
+            const int q = e - FX;
+            lx = q % TX; lz = q / TX; ly = TY - 1; step = c.d.nx; ok = hy;
+        } else {
+            const int q = e - FX - FY;
+            lx = q % TX; ly = q / TX; lz = TZ - 1; step = c.sxy; ok = hz;
+        }
+        if (!ok || lx >= c.ex || ly >= c.ey || lz >= c.ez) continue;
+        const uint32_t a = off + (uint32_t)((c.x0 + lx) + (int64_t)c.d.nx * (c.y0 + ly) + c.sxy * (c.z0 + lz));
+        const uint32_t b = a + (uint32_t)step;
+        const uint32_t za = lbl[a], zb = lbl[b];
+        if (za >= M || zb >= M) { err |= ST_CORRUPT; continue; }
+        const uint64_t ka = vkey(f, a), kb = vkey(f, b);
+        const bool up = kb < ka;  // the upper end is the saddle
+        gmerge(slot, mkey, f, M, n, za, up ? a : b, up ? ka : kb, zb, cap, err);
+    }
+    if (err) atomicOr(&h->status, err);
+}
+
+// ---------------------------------------------------------------------------
+// 3. Repair (Alg. 4, 5)
+
+// Representative: follow the slots from x while the saddle is at or below
+// `level` and x is no root; the last minimum reached.
+__device__ __forceinline__ uint32_t chase(Slot *__restrict__ S, const float *__restrict__ f, uint32_t M, uint32_t n,
+                                          uint32_t x, uint64_t level, uint32_t cap, uint32_t &err)
+{
+    for (uint32_t step = 0; step < cap; ++step) {
+        const uint64_t t = ld_relaxed(&S[x].w);
+        const uint32_t v = hi32(t), s = lo32(t);
+        if (v >= M || s >= n) { err |= ST_CORRUPT; return x; }
+        if (v == x) return x;
+        if (saddle_key(S, f, x, s) > level) return x;
+        x = v;
+    }
+    err |= ST_LIVELOCK;
+    return x;
+}
+
+__global__ __launch_bounds__(kBlock) void k_repair_min(const float *__restrict__ f, Slot *__restrict__ S, uint32_t n,
+                                                       uint32_t cap, Header *__restrict__ h)
+{
+    const uint32_t M = h->n_minima;
+    uint32_t err = 0;
+    for (uint32_t m = blockIdx.x * kBlock + threadIdx.x; m < M; m += gridDim.x * kBlock) {
+        const uint64_t t = ld_relaxed(&S[m].w);
+        const uint32_t v = hi32(t), s = lo32(t);
+        if (v == m) continue;
+        if (v >= M || s >= n) { err |= ST_CORRUPT; continue; }
+        const uint32_t r = chase(S, f, M, n, v, saddle_key(S, f, m, s), cap, err);
+        if (r != v) st_relaxed(&S[m].w, pack(s, r));
+    }
+    if (err) atomicOr(&h->status, err);
+}
+
+// Output triplets in vertex order, field-local ids.  A local minimum copies
+// its own (repaired) triplet; any other vertex u gets (u, u, representative
+// of its local minimum at the level of u).  Also counts pairs and roots per
+// chunk.
+__global__ __launch_bounds__(kBlock) void k_repair_reg(const float *__restrict__ f, const uint32_t *__restrict__ lbl,
+                                                       Slot *__restrict__ S, const uint64_t *__restrict__ mkey,
+                                                       uint64_t *__restrict__ T, uint32_t *__restrict__ pcnt,
+                                                       const FieldDesc *__restrict__ D, const int64_t *__restrict__ cs,
+                                                       int nf, uint32_t n, uint32_t cap, Header *__restrict__ h)
+{
+    __shared__ uint32_t sp[kBlock / 64], sr[kBlock / 64];
+    const int64_t c = blockIdx.x;
+    const FieldDesc d = D[search(cs, nf, c)];
+    const int64_t lo = (c - d.chunk_start) * kChunk;
+    const int64_t hi = min(lo + (int64_t)kChunk, d.n);
+    const uint32_t off = (uint32_t)d.offset;
+    const uint32_t M = h->n_minima;
+    uint32_t err = 0, np = 0, nr = 0;
+    for (int64_t j = lo + threadIdx.x; j < hi; j += kBlock) {
+        const uint32_t u = off + (uint32_t)j;
+        const uint32_t z = lbl[u];
+        if (z >= M) { err |= ST_CORRUPT; continue; }
+        uint32_t s, r;
+        if (lo32(mkey[z]) == u) {  // u is a local minimum
+            const uint64_t t = S[z].w;
+            s = lo32(t);
+            r = hi32(t);
+            if (r >= M || s >= n) { err |= ST_CORRUPT; continue; }
+            np += (s != u);
+            nr += (r == z);
+        } else {
+            s = u;
+            r = chase(S, f, M, n, z, vkey(f, u), cap, err);
+        }
+        const uint32_t gr = lo32(mkey[r]);
+        if (gr >= n) { err |= ST_CORRUPT; continue; }
+        T[u] = pack(s - off, gr - off);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        np += __shfl_xor(np, o);
+        nr += __shfl_xor(nr, o);
+    }
+    if ((threadIdx.x & 63) == 0) { sp[threadIdx.x >> 6] = np; sr[threadIdx.x >> 6] = nr; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t a = 0, b = 0;
+        for (int w = 0; w < kBlock / 64; ++w) { a += sp[w]; b += sr[w]; }
+        pcnt[c] = a;
+        if (b) atomicAdd((unsigned long long *)&h->roots, (unsigned long long)b);
+    }
+    if (err) atomicOr(&h->status, err);
+}
+
+// ---------------------------------------------------------------------------
+// 5. Pairs: one per branch (Sec. 1), i.e. every u with T[u] = (s, v), s != u.
+
+// Ids read from T are checked to lie in the field; a bad one is no pair and
+// latches ST_CORRUPT.
+__device__ __forceinline__ bool classify(const uint64_t *__restrict__ T, uint32_t off, uint32_t nloc, int64_t j,
+                                         uint32_t &s_out, bool &root, uint32_t &err)
+{
+    const uint64_t t = T[off + (uint32_t)j];
+    const uint32_t s = lo32(t), v = hi32(t);
+    root = false;
+    if (s >= nloc || v >= nloc) { err |= ST_CORRUPT; return false; }
+    if (s == (uint32_t)j) { root = (v == (uint32_t)j); return false; }
+    s_out = s;
+    return true;
+}
+
+__global__ __launch_bounds__(kBlock) void k_pairs_count(const uint64_t *__restrict__ T,
+                                                        const FieldDesc *__restrict__ D, const int64_t *__restrict__ cs,
+                                                        int nf, uint32_t *__restrict__ cnt, Header *__restrict__ h)
+{
+    __shared__ uint32_t sp[kBlock / 64], sr[kBlock / 64];
+    const int64_t c = blockIdx.x;
+    const FieldDesc d = D[search(cs, nf, c)];
+    const int64_t lo = (c - d.chunk_start) * kChunk;
+    const int64_t hi = min(lo + (int64_t)kChunk, d.n);
+    uint32_t np = 0, nr = 0, err = 0;
+    for (int64_t j = lo + threadIdx.x; j < hi; j += kBlock) {
+        uint32_t s;
+        bool root;
+        np += classify(T, (uint32_t)d.offset, (uint32_t)d.n, j, s, root, err) ? 1u : 0u;
+        nr += root ? 1u : 0u;
+    }
+    if (err) atomicOr(&h->status, err);
+    for (int o = 32; o > 0; o >>= 1) {
+        np += __shfl_xor(np, o);
+        nr += __shfl_xor(nr, o);
+    }
+    if ((threadIdx.x & 63) == 0) { sp[threadIdx.x >> 6] = np; sr[threadIdx.x >> 6] = nr; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t a = 0, b = 0;
+        for (int w = 0; w < kBlock / 64; ++w) { a += sp[w]; b += sr[w]; }
+        cnt[c] = a;
+        if (b) atomicAdd((unsigned long long *)&h->roots, (unsigned long long)b);
+    }
+}
+
+// Exclusive scan of the chunk counts (one workgroup of 1024), the total, and
+// the per-field pair offsets.
+__global__ __launch_bounds__(1024) void k_pairs_scan(uint32_t *__restrict__ cnt, int64_t n_chunks,
+                                                     const FieldDesc *__restrict__ D, int nf,
+                                                     int64_t *__restrict__ pair_offsets, int64_t capacity,
+                                                     Header *__restrict__ h)
+{
+    __shared__ uint64_t part[1024];
+    const int tid = threadIdx.x;
+    const int64_t per = (n_chunks + 1023) / 1024;
+    const int64_t a = min((int64_t)tid * per, n_chunks), b = min(a + per, n_chunks);
+    uint64_t s = 0;
+    for (int64_t i = a; i < b; ++i) s += cnt[i];
+    part[tid] = s;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        const uint64_t v = tid >= o ? part[tid - o] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    uint64_t run = part[tid] - s;
+    for (int64_t i = a; i < b; ++i) {
+        const uint32_t v = cnt[i];
+        cnt[i] = (uint32_t)run;
+        run += v;
+    }
+    const uint64_t total = part[1023];
+    __syncthreads();
+    if (pair_offsets) {
+        for (int i = tid; i < nf; i += 1024) pair_offsets[i] = cnt[D[i].chunk_start];
+        if (tid == 0) pair_offsets[nf] = (int64_t)total;
+    }
+    if (tid == 0) {
+        h->total_pairs = (int64_t)total;
+        if ((int64_t)total > capacity) atomicOr(&h->status, ST_CAPACITY);
+    }
+}
+
+// Ordered compaction: ascending vertex id within the chunk, chunks in order.
+__global__ __launch_bounds__(kBlock) void k_pairs_write(const float *__restrict__ f, const uint64_t *__restrict__ T,
+                                                        const FieldDesc *__restrict__ D, const int64_t *__restrict__ cs,
+                                                        int nf, const uint32_t *__restrict__ base, int64_t capacity,
+                                                        uint32_t *__restrict__ birth, uint32_t *__restrict__ death,
+                                                        float *__restrict__ bval, float *__restrict__ dval)
+{
+    __shared__ uint32_t wsum[kBlock / 64];
+    const int64_t c = blockIdx.x;
+    const FieldDesc d = D[search(cs, nf, c)];
+    const int64_t lo = (c - d.chunk_start) * kChunk;
+    const int64_t hi = min(lo + (int64_t)kChunk, d.n);
+    const uint32_t off = (uint32_t)d.offset;
+    const int wave = threadIdx.x >> 6;
+    int64_t run = base[c];
+    for (int64_t r0 = lo; r0 < hi; r0 += kBlock) {
+        const int64_t j = r0 + threadIdx.x;
+        bool p = false;
+        uint32_t s_loc = 0;
+        if (j < hi) {
+            bool root;
+            uint32_t err = 0;
+            p = classify(T, off, (uint32_t)d.n, j, s_loc, root, err);
+        }
+        const uint64_t m = __ballot(p);
+        if ((threadIdx.x & 63) == 0) wsum[wave] = (uint32_t)__popcll(m);
+        __syncthreads();
+        uint32_t wb = 0, tot = 0;
+        for (int w = 0; w < kBlock / 64; ++w) {
+            wb += (w < wave) ? wsum[w] : 0u;
+            tot += wsum[w];
+        }
+        if (p) {
+            const int64_t pos = run + wb + (uint32_t)__popcll(m & lanemask_lt());
+            if (pos < capacity) {
+                birth[pos] = (uint32_t)j;
+                death[pos] = s_loc;
+                bval[pos] = f[off + (uint32_t)j];
+                dval[pos] = f[off + s_loc];
+            }
+        }
+        run += tot;
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 6. Adjoint of the pair readout
+
+__global__ void k_fill0(float *__restrict__ g, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) g[i] = 0.0f;
+}
+
+struct BwdGroup {
+    int64_t voff[kBwdGroup];  // vertex offset of each field of the group
+    int64_t nv[kBwdGroup];    // vertices of each field of the group
+    int32_t first, count;
+};
+
+// grad[birth] += gb (birth vertices are distinct and are never death
+// vertices, so a plain update is race free); grad[death] += gd atomically.
+__global__ __launch_bounds__(kBlock) void k_scatter(BwdGroup g, const int64_t *__restrict__ po, int64_t capacity,
+                                                    const uint32_t *__restrict__ birth,
+                                                    const uint32_t *__restrict__ death,
+                                                    const float *__restrict__ gb, const float *__restrict__ gd,
+                                                    float *__restrict__ grad)
+{
+    const int64_t k0 = po[g.first];
+    const int64_t k1 = min(po[g.first + g.count], capacity);
+    for (int64_t k = k0 + (int64_t)blockIdx.x * kBlock + threadIdx.x; k < k1; k += (int64_t)gridDim.x * kBlock) {
+        int lo = 0, hi = g.count;  // po[first+lo] <= k < po[first+hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (po[g.first + mid] <= k) lo = mid; else hi = mid;
+        }
+        const int64_t vo = g.voff[lo];
+        const uint32_t bk = birth[k], dk = death[k];
+        if ((int64_t)bk >= g.nv[lo] || (int64_t)dk >= g.nv[lo]) continue;  // not an id of this field
+        grad[vo + bk] += gb[k];
+        unsafeAtomicAdd(grad + vo + dk, gd[k]);
+    }
+}
+
+}  // namespace mtd

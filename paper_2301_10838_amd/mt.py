@@ -28,7 +28,9 @@ STATUS_NAMES = {
 }
 EXPORTS = [
     "mt_status_string", "mt_workspace_bytes", "mt_batch_workspace_bytes", "mt_build", "mt_persistence_pairs",
-    "mt_batch_build", "mt_sync_status", "mt_pairs_backward", "mt_release_caches",
+    "mt_batch_build", "mt_sync_status", "mt_build_stats", "mt_pairs_backward", "mt_release_caches",
+    "mt_profile_begin",
+    "mt_profile_end", "mt_profile_count", "mt_profile_get",
 ]
 
 
@@ -64,10 +66,20 @@ def load_library():
     lib.mt_batch_build.restype = ctypes.c_int
     lib.mt_sync_status.argtypes = [P, P, P, P]
     lib.mt_sync_status.restype = ctypes.c_int
+    lib.mt_build_stats.argtypes = [P, P, P]
+    lib.mt_build_stats.restype = ctypes.c_int
     lib.mt_pairs_backward.argtypes = [P, I32, P, I64, P, P, P, P, P, ctypes.c_int, P]
     lib.mt_pairs_backward.restype = ctypes.c_int
     lib.mt_release_caches.argtypes = []
     lib.mt_release_caches.restype = None
+    lib.mt_profile_begin.argtypes = []
+    lib.mt_profile_begin.restype = ctypes.c_int
+    lib.mt_profile_end.argtypes = []
+    lib.mt_profile_end.restype = ctypes.c_int
+    lib.mt_profile_count.argtypes = []
+    lib.mt_profile_count.restype = ctypes.c_int
+    lib.mt_profile_get.argtypes = [ctypes.c_int, ctypes.c_char_p, SZ, P, P]
+    lib.mt_profile_get.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -279,6 +291,32 @@ class MergeTreePairs(torch.autograd.Function):
         grad = torch.empty(plan.n_total, dtype=torch.float32, device=dev)
         mt_pairs_backward(plan._dims_c, len(plan.dims), offsets, P, birth, death, gb, gd, grad)
         return grad, None
+
+
+def profile_begin():
+    _check(load_library().mt_profile_begin(), "mt_profile_begin")
+
+
+def profile_end():
+    """Stop per-kernel timing; returns {kernel name: (total ms, launches)}."""
+    lib = load_library()
+    _check(lib.mt_profile_end(), "mt_profile_end")
+    out = {}
+    buf = ctypes.create_string_buffer(128)
+    for i in range(lib.mt_profile_count()):
+        ms = ctypes.c_double(0.0)
+        n = ctypes.c_int64(0)
+        _check(lib.mt_profile_get(i, buf, 128, ctypes.byref(ms), ctypes.byref(n)), "mt_profile_get")
+        out[buf.value.decode()] = (ms.value, n.value)
+    return out
+
+
+def build_stats(workspace: torch.Tensor) -> int:
+    """Tile-local minima of the last build on this workspace (synchronizes)."""
+    n = ctypes.c_int64(0)
+    _check(load_library().mt_build_stats(workspace.data_ptr(), _stream_ptr(workspace.device), ctypes.byref(n)),
+           "mt_build_stats")
+    return n.value
 
 
 def release_caches():

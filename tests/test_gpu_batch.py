@@ -1,0 +1,149 @@
+"""Batched form: many uneven fields in one graph launch, bit-exact per field."""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import device, gpu_tree, u32
+from paper_2301_10838_amd import fields
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return device()
+
+
+def _check_plan(plan, fs):
+    offs = plan.pair_offsets.cpu().numpy()
+    T_all = u32(plan.triplets).reshape(-1, 2)
+    b_all, d_all = u32(plan.birth), u32(plan.death)
+    bv_all, dv_all = plan.bval.cpu().numpy(), plan.dval.cpu().numpy()
+    assert offs[0] == 0
+    for i, f in enumerate(fs):
+        a, b = plan.vertex_offsets[i], plan.vertex_offsets[i + 1]
+        T_ref = oracle.merge_tree(f)
+        assert np.array_equal(T_all[a:b], T_ref), f"field {i} {f.shape}"
+        rb, rd, rbv, rdv, _ = oracle.pairs(f, T_ref)
+        p0, p1 = offs[i], offs[i + 1]
+        assert p1 - p0 == rb.size, f"field {i}"
+        assert np.array_equal(b_all[p0:p1], rb) and np.array_equal(d_all[p0:p1], rd), f"field {i}"
+        flat = f.reshape(-1).astype(np.float32)
+        assert np.array_equal(bv_all[p0:p1].view(np.uint32), flat[rb].view(np.uint32))
+        assert np.array_equal(dv_all[p0:p1].view(np.uint32), flat[rd].view(np.uint32))
+
+
+def _mixed_fields(seed=0):
+    rng = np.random.default_rng(seed)
+    fs = [
+        fields.lognormal_grf((37, 29, 45), 101),
+        rng.random((1,)).astype(np.float32),
+        fields.lognormal_grf((300, 257), 102),
+        fields.uniform((5001,), 103),
+        rng.integers(0, 3, (7, 1, 9)).astype(np.float32),
+        fields.bumps((33, 40, 21), 104, n_bumps=8, sigma=(2, 6)),
+        rng.integers(0, 4, (17, 130)).astype(np.float32),
+        np.full((4, 4, 4), 1.5, np.float32),
+        fields.uniform((2, 3), 105),
+    ]
+    return fs
+
+
+def test_mixed_batch_matches_oracle(dev):
+    import paper_2301_10838_amd.mt as mt
+
+    fs = _mixed_fields()
+    plan = mt.mt_batch_build([torch.from_numpy(f).to(dev) for f in fs])
+    torch.cuda.synchronize()
+    _check_plan(plan, fs)
+
+
+def test_batched_equals_plain(dev):
+    import paper_2301_10838_amd.mt as mt
+
+    fs = fields.workload("batch48", scale=0.25)
+    plan = mt.mt_batch_build([torch.from_numpy(f).to(dev) for f in fs])
+    torch.cuda.synchronize()
+    offs = plan.pair_offsets.cpu().numpy()
+    T_all = u32(plan.triplets).reshape(-1, 2)
+    b_all = u32(plan.birth)
+    for i, f in enumerate(fs):
+        T, prs = gpu_tree(f, dev)
+        a, b = plan.vertex_offsets[i], plan.vertex_offsets[i + 1]
+        assert np.array_equal(T_all[a:b], T), i
+        assert np.array_equal(b_all[offs[i]:offs[i + 1]], prs[0]), i
+    _check_plan(plan, fs[:12])
+
+
+def test_graph_replays_follow_new_inputs(dev):
+    """The cached graph is replayed with eager work and new field contents in
+    between; every replay must match the oracle for the current contents."""
+    import paper_2301_10838_amd.mt as mt
+
+    shapes = [(20, 18, 16), (64, 50), (300,)]
+    plan = mt.BatchPlan(shapes, dev)
+    for rep in range(4):
+        fs = [fields.lognormal_grf(s, 200 + 10 * rep + i) for i, s in enumerate(shapes)]
+        plan.load([torch.from_numpy(f).to(dev) for f in fs])
+        scratch = torch.randn(1 << 20, device=dev)
+        scratch.mul_(2.0).sum().item()  # eager work between replays
+        plan.launch()
+        plan.sync_status()
+        _check_plan(plan, fs)
+
+
+def test_batch_capacity_latched(dev):
+    import paper_2301_10838_amd.mt as mt
+
+    fs = [fields.uniform((20, 20, 20), 7), fields.uniform((30, 30), 8)]
+    plan = mt.BatchPlan([f.shape for f in fs], dev, pair_capacity=50)
+    plan.load([torch.from_numpy(f).to(dev) for f in fs])
+    plan.launch()
+    with pytest.raises(mt.MTError) as e:
+        plan.sync_status()
+    assert e.value.status == -4
+    want = sum(oracle.pairs(f, oracle.merge_tree(f))[0].size for f in fs)
+    assert int(plan.pair_offsets[-1]) == want
+    # the first `capacity` pairs are still the right ones
+    rb0 = oracle.pairs(fs[0], oracle.merge_tree(fs[0]))[0]
+    assert np.array_equal(u32(plan.birth)[:50], rb0[:50])
+
+
+def test_batch48_workload(dev):
+    """Full uneven batch: batched == plain for every field, oracle on a subset."""
+    import paper_2301_10838_amd.mt as mt
+
+    fs = fields.workload("batch48")
+    print("case batch48", sum(f.size for f in fs), flush=True)
+    plan = mt.mt_batch_build([torch.from_numpy(f).to(dev) for f in fs])
+    torch.cuda.synchronize()
+    offs = plan.pair_offsets.cpu().numpy()
+    T_all = u32(plan.triplets).reshape(-1, 2)
+    for i, f in enumerate(fs):
+        T, prs = gpu_tree(f, dev)
+        a, b = plan.vertex_offsets[i], plan.vertex_offsets[i + 1]
+        assert np.array_equal(T_all[a:b], T), i
+        assert offs[i + 1] - offs[i] == prs[0].size, i
+    small = sorted(range(len(fs)), key=lambda i: fs[i].size)[:10]
+    sub = [fs[i] for i in small]
+    for i in small:
+        f = fs[i]
+        a, b = plan.vertex_offsets[i], plan.vertex_offsets[i + 1]
+        assert np.array_equal(T_all[a:b], oracle.merge_tree(f)), i
+
+
+def test_batch_abi_rejects_bad_workspace(dev):
+    import paper_2301_10838_amd.mt as mt
+
+    lib = mt.load_library()
+    dims = (ctypes.c_int64 * 6)(8, 8, 8, 10, 10, 1)
+    need = lib.mt_batch_workspace_bytes(dims, 2)
+    ws = torch.empty(need - 256, dtype=torch.uint8, device=dev)
+    x = torch.empty(1024, device=dev)
+    rc = lib.mt_batch_build(x.data_ptr(), dims, 2, x.data_ptr(), x.data_ptr(), x.data_ptr(), x.data_ptr(),
+                            x.data_ptr(), 10, x.data_ptr(), ws.data_ptr(), ws.numel(),
+                            torch.cuda.current_stream().cuda_stream)
+    assert rc == -6

@@ -29,7 +29,7 @@ def _fields_tiny():
     return out
 
 
-@pytest.mark.parametrize("variant", ["paper", "prelink", "basins"])
+@pytest.mark.parametrize("variant", ["paper", "prelink", "basins", "tiles", "tile_trees"])
 def test_interleavings_reach_oracle(variant):
     for i, f in enumerate(_fields_tiny()):
         want = oracle.merge_tree(f)
@@ -76,3 +76,16 @@ def test_prelink_is_a_reachable_state():
             for _ in tmt_sim.merge_thread(T, key, u, u, int(w[u])):
                 pass
     assert T == [(u, int(w[u])) if w[u] != u else (u, u) for u in range(f.size)]
+
+
+@pytest.mark.parametrize("variant", ["tiles", "tile_trees"])
+@pytest.mark.parametrize("box", [(1, 1, 1), (2, 2, 2), (3, 2, 1), (4, 4, 4)])
+def test_two_level_boxes(box, variant):
+    rng = np.random.default_rng(9)
+    for i in range(6):
+        shape = [(5, 6, 4), (7, 9), (20,)][i % 3]
+        f = rng.integers(0, 4, size=shape).astype(np.float32) if i % 2 else rng.random(shape).astype(np.float32)
+        want = oracle.merge_tree(f)
+        for seed in range(4):
+            got = tmt_sim.simulate(f, seed=seed, variant=variant, box=box)
+            assert np.array_equal(got, want), (variant, box, i, seed)

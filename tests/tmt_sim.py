@@ -29,6 +29,18 @@ Variants used by the GPU design, each checked to give the same unique T:
   z(u) reached by steepest descent, T[u] = (u, z(u)); an edge whose ends
   descend to the same minimum is already implied and is skipped, and the
   other edges are merged between the two minima, Merge(z(a), max(a, b), z(b)).
+- ``tiles``: as basins, in two levels.  The grid is cut into boxes and every
+  minimum belongs to the box holding it.  First, for every box on its own,
+  the edges owned by the box's vertices whose two minima both belong to that
+  box are merged (interleaved within the box), then those minima are
+  repaired; every other edge is merged afterwards, and a final repair runs
+  over all vertices.
+- ``tile_trees``: the grid is cut into boxes; every box first builds the
+  merge tree of its own subgraph (steepest descent inside the box, chains
+  compressed to the box-local minimum, every edge inside the box merged
+  between box-local minima, then those minima repaired); afterwards the
+  edges that cross box faces are merged between the box-local minima of
+  their ends, and a final repair runs over all vertices.
 """
 from __future__ import annotations
 
@@ -157,8 +169,22 @@ def steepest_lower(flat, shape):
     return w
 
 
+def _box_of(shape, box):
+    """Box index of every vertex for a box shape given in (x, y, z) order."""
+    idx = np.indices(shape)  # (z, y, x) or lower rank, numpy axis order
+    nd = len(shape)
+    coords = [idx[nd - 1 - d] // box[d] for d in range(nd)]  # x, y, z
+    nb = [(shape[nd - 1 - d] + box[d] - 1) // box[d] for d in range(nd)]
+    b = np.zeros(shape, dtype=np.int64)
+    mul = 1
+    for d in range(nd):
+        b += coords[d] * mul
+        mul *= nb[d]
+    return b.ravel()
+
+
 def simulate(f, seed=0, variant="paper", edge_order=None, serial=False,
-             root_guard=True, skip_root_remerge=True, return_last=True):
+             root_guard=True, skip_root_remerge=True, return_last=True, box=(2, 2, 2)):
     """Run Alg. 1 (or a variant) under one seeded interleaving; returns T [N, 2]."""
     f = np.asarray(f)
     shape = f.shape
@@ -176,7 +202,43 @@ def simulate(f, seed=0, variant="paper", edge_order=None, serial=False,
         for a, b in edges:
             hi, lo = (a, b) if key(b) < key(a) else (b, a)
             merges.append((hi, hi, lo))
-    elif variant in ("prelink", "basins"):
+    elif variant == "tile_trees":
+        bx = _box_of(shape, box[: len(shape)])
+        nb = neighbours(shape)
+        zl = np.arange(N)
+        for u in range(N):  # steepest descent inside the box
+            best = u
+            for x in nb[u]:
+                if bx[x] == bx[u] and key(x) < key(best):
+                    best = x
+            zl[u] = best
+        for u in range(N):
+            T[u] = (u, int(zl[u])) if zl[u] != u else (u, u)
+        for it in range(N):
+            z2 = zl[zl]
+            if np.array_equal(z2, zl):
+                break
+            zl = z2
+        for u in range(N):
+            if zl[u] != u:
+                T[u] = (u, int(zl[u]))
+        local = {}
+        for a, b in edges:
+            hi = a if key(b) < key(a) else b
+            m = (int(zl[a]), hi, int(zl[b]))
+            if bx[a] == bx[b]:
+                if zl[a] != zl[b]:
+                    local.setdefault(int(bx[a]), []).append(m)
+            else:
+                merges.append(m)
+        boxes = list(local.items())
+        rng.shuffle(boxes)
+        for bidx, ms in boxes:
+            th = [merge_thread(T, key, u, s_, v, root_guard, skip_root_remerge) for (u, s_, v) in ms]
+            run_phase(th, rng)
+            mins = [u for u in range(N) if zl[u] == u and bx[u] == bidx]
+            run_phase([repair_thread(T, key, u, return_last) for u in mins], rng)
+    elif variant in ("prelink", "basins", "tiles"):
         w = steepest_lower(flat, shape)
         for u in range(N):
             T[u] = (u, int(w[u])) if w[u] != u else (u, u)
@@ -196,11 +258,32 @@ def simulate(f, seed=0, variant="paper", edge_order=None, serial=False,
             for u in range(N):
                 if z[u] != u:
                     T[u] = (u, int(z[u]))
-            for a, b in edges:
-                if z[a] == z[b]:
-                    continue  # implied by the two descents
-                hi = a if key(b) < key(a) else b
-                merges.append((int(z[a]), hi, int(z[b])))
+            if variant == "basins":
+                for a, b in edges:
+                    if z[a] == z[b]:
+                        continue  # implied by the two descents
+                    hi = a if key(b) < key(a) else b
+                    merges.append((int(z[a]), hi, int(z[b])))
+            else:
+                bx = _box_of(shape, box[: len(shape)])
+                local = {}
+                for a, b in edges:
+                    if z[a] == z[b]:
+                        continue
+                    hi = a if key(b) < key(a) else b
+                    own = min(a, b)  # the edge belongs to its lower-id end's box
+                    m = (int(z[a]), hi, int(z[b]))
+                    if bx[z[a]] == bx[own] and bx[z[b]] == bx[own]:
+                        local.setdefault(int(bx[own]), []).append(m)
+                    else:
+                        merges.append(m)
+                boxes = list(local.items())
+                rng.shuffle(boxes)
+                for bidx, ms in boxes:
+                    th = [merge_thread(T, key, u, s_, v, root_guard, skip_root_remerge) for (u, s_, v) in ms]
+                    run_phase(th, rng)
+                    mins = [u for u in range(N) if z[u] == u and bx[u] == bidx]
+                    run_phase([repair_thread(T, key, u, return_last) for u in mins], rng)
     else:
         raise ValueError(variant)
 
