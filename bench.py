@@ -256,6 +256,8 @@ def main():
     ap.add_argument("--workload", default="grf512")
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (3 times), the reference for HBM counters")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -327,6 +329,14 @@ def main():
         "path_algo_GBps": path_bytes / dt / 1e9,
         "kernels": per_kernel,
     }
+    if args.calibrate_copy:
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = {"read": src.numel() * 4, "write": dst.numel() * 4}
+        del src, dst
     if not args.no_secondary:
         out["secondary"] = {"batched": bench_batch(dev, mt, lib), "backward": bench_backward(dev, mt)}
     if not args.no_cpu:

@@ -295,12 +295,16 @@ __global__ __launch_bounds__(S::NT) void k_local(const float *__restrict__ f, ui
                                                  Header *__restrict__ h)
 {
     constexpr int NT = S::NT, VOL = S::VOL, TX = S::TX, TY = S::TY;
+    constexpr int HALF = VOL / 2;   // local minima are pairwise non-adjacent: at most half the tile
+    constexpr int H = VOL / 2;      // hash table of basin pairs
     static_assert(VOL <= 65536, "positions fit 16 bits");
     __shared__ uint32_t hk[VOL];    // order key of every tile vertex
     __shared__ int16_t wl[VOL];     // lowest lower neighbour in the tile (self at a local minimum)
     __shared__ uint16_t zl[VOL];    // local minimum index of the vertex's local basin
-    __shared__ uint32_t TL[VOL];    // triplets of the local minima
-    __shared__ uint16_t mh[VOL];    // tile position of local minimum i
+    __shared__ uint32_t TL[HALF];   // triplets of the local minima
+    __shared__ uint16_t mh[HALF];   // tile position of local minimum i
+    __shared__ uint32_t hpair[H];   // basin pair (lo | hi << 16) of each table entry
+    __shared__ uint64_t hbest[H];   // lowest key of an edge joining that pair
     __shared__ uint32_t wsum[NT / 64];
     __shared__ uint32_t sb0;
 
@@ -378,6 +382,11 @@ __global__ __launch_bounds__(S::NT) void k_local(const float *__restrict__ f, ui
     const uint32_t cnt = run;
     if (threadIdx.x == 0) sb0 = atomicAdd(&h->n_minima, cnt);
 
+    for (int i = threadIdx.x; i < H; i += NT) {
+        hpair[i] = 0xffffffffu;
+        hbest[i] = ~0ull;
+    }
+
     // local basins: follow the pointers to the local minimum (keys fall
     // strictly along them, so at most VOL steps)
     for (int p = threadIdx.x; p < VOL; p += NT) {
@@ -398,7 +407,12 @@ __global__ __launch_bounds__(S::NT) void k_local(const float *__restrict__ f, ui
         return;
     }
 
-    // merge every edge inside the tile whose ends lie in different local basins
+    // Edges inside the tile whose ends lie in different local basins.  Of all
+    // edges joining the same two basins only the lowest (smallest upper end)
+    // is merged: the connection it makes at its level implies the connection
+    // every other one would make at a higher level.  A table keyed by the
+    // basin pair keeps that lowest edge; an edge that finds no table room is
+    // merged directly.
     uint32_t err = 0;
     for (int p = threadIdx.x; p < VOL; p += NT) {
         const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
@@ -408,12 +422,36 @@ __global__ __launch_bounds__(S::NT) void k_local(const float *__restrict__ f, ui
 #define MT_EDGE(cond, q)                                                                    \
         if (cond) {                                                                         \
             const uint32_t zb = zl[(q)];                                                   \
-            if (zb != za) lds_merge<VOL>(TL, hk, mh, za, tkey(hk, (q)) < ka ? p : (q), zb, cap, err); \
+            if (zb != za) {                                                                \
+                const uint64_t kb = tkey(hk, (q));                                         \
+                const uint64_t ks = kb < ka ? ka : kb;                                     \
+                const uint32_t key = min(za, zb) | (max(za, zb) << 16);                   \
+                uint32_t slot_i = (key * 0x9E3779B1u) >> (32 - __builtin_ctz(H));          \
+                bool placed = false;                                                       \
+                for (int probe = 0; probe < 32; ++probe) {                                 \
+                    uint32_t prev = 0xffffffffu;                                           \
+                    __hip_atomic_compare_exchange_strong(hpair + slot_i, &prev, key,       \
+                        __ATOMIC_RELAXED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); \
+                    if (prev == 0xffffffffu || prev == key) {                              \
+                        atomicMin((unsigned long long *)(hbest + slot_i), (unsigned long long)ks); \
+                        placed = true;                                                     \
+                        break;                                                             \
+                    }                                                                      \
+                    slot_i = (slot_i + 1) & (H - 1);                                       \
+                }                                                                          \
+                if (!placed) lds_merge<HALF>(TL, hk, mh, za, (uint32_t)lo32(ks), zb, cap, err); \
+            }                                                                              \
         }
         MT_EDGE(lx + 1 < c.ex, p + 1)
         MT_EDGE(ly + 1 < c.ey, p + TX)
         MT_EDGE(lz + 1 < c.ez, p + TX * TY)
 #undef MT_EDGE
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < H; i += NT) {
+        const uint32_t key = hpair[i];
+        if (key == 0xffffffffu) continue;
+        lds_merge<HALF>(TL, hk, mh, key & 0xffffu, (uint32_t)lo32(hbest[i]), key >> 16, cap, err);
     }
     __syncthreads();
 
@@ -493,6 +531,17 @@ __device__ void gmerge(Slot *__restrict__ S, const uint64_t *__restrict__ mkey, 
     err |= ST_LIVELOCK;
 }
 
+constexpr int pow2_at_least(int v)
+{
+    int p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+// Per tile: the edges leaving through its +x, +y, +z faces.  A local basin
+// lies inside one tile, so all edges joining the same two local basins cross
+// the same face and meet in this workgroup; only the lowest of them (smallest
+// upper end) is merged, the others add nothing above its level.
 template <class S>
 __global__ __launch_bounds__(S::NT) void k_cross(const float *__restrict__ f, const uint32_t *__restrict__ lbl,
                                                  Slot *__restrict__ slot, const uint64_t *__restrict__ mkey,
@@ -502,13 +551,22 @@ __global__ __launch_bounds__(S::NT) void k_cross(const float *__restrict__ f, co
                                                  Header *__restrict__ h)
 {
     constexpr int TX = S::TX, TY = S::TY, TZ = S::TZ;
-    constexpr int FX = TY * TZ, FY = TX * TZ, FZ = TX * TY;
+    // faces that can have a neighbour: a 2-D shape has no z face, a 1-D one no y face
+    constexpr int FX = TY * TZ, FY = TY > 1 ? TX * TZ : 0, FZ = TZ > 1 ? TX * TY : 0;
+    constexpr int H = pow2_at_least(2 * (FX + FY + FZ)) < 2048 ? pow2_at_least(2 * (FX + FY + FZ)) : 2048;
+    __shared__ uint64_t hpair[H];  // (lower number | higher number << 32)
+    __shared__ uint64_t hbest[H];  // lowest upper-end key of an edge joining that pair
     const int64_t tl = xcd_tile(blockIdx.x, gridDim.x, remap);
     if (tl >= ntiles) return;
     const TileCtx c = tile_ctx<S>(D, tfield, tstart, nfc, tile0 + tl);
     const uint32_t off = (uint32_t)c.d.offset;
     const bool hx = c.x0 + TX < c.d.nx, hy = c.y0 + TY < c.d.ny, hz = c.z0 + TZ < c.d.nz;
     const uint32_t M = h->n_minima;
+    for (int i = threadIdx.x; i < H; i += S::NT) {
+        hpair[i] = ~0ull;
+        hbest[i] = ~0ull;
+    }
+    __syncthreads();
     uint32_t err = 0;
     for (int e = threadIdx.x; e < FX + FY + FZ; e += S::NT) {
         int lx, ly, lz;
@@ -529,8 +587,29 @@ __global__ __launch_bounds__(S::NT) void k_cross(const float *__restrict__ f, co
         const uint32_t za = lbl[a], zb = lbl[b];
         if (za >= M || zb >= M) { err |= ST_CORRUPT; continue; }
         const uint64_t ka = vkey(f, a), kb = vkey(f, b);
-        const bool up = kb < ka;  // the upper end is the saddle
-        gmerge(slot, mkey, f, M, n, za, up ? a : b, up ? ka : kb, zb, cap, err);
+        const uint64_t ks = kb < ka ? ka : kb;  // the upper end is the saddle
+        const uint64_t key = (uint64_t)min(za, zb) | ((uint64_t)max(za, zb) << 32);
+        uint32_t si = (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> (64 - __builtin_ctz(H)));
+        bool placed = false;
+        for (int probe = 0; probe < 32; ++probe) {
+            uint64_t prev = ~0ull;
+            __hip_atomic_compare_exchange_strong(hpair + si, &prev, key, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (prev == ~0ull || prev == key) {
+                atomicMin((unsigned long long *)(hbest + si), (unsigned long long)ks);
+                placed = true;
+                break;
+            }
+            si = (si + 1) & (H - 1);
+        }
+        if (!placed) gmerge(slot, mkey, f, M, n, za, lo32(ks), ks, zb, cap, err);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < H; i += S::NT) {
+        const uint64_t key = hpair[i];
+        if (key == ~0ull) continue;
+        const uint64_t ks = hbest[i];
+        gmerge(slot, mkey, f, M, n, lo32(key), lo32(ks), ks, hi32(key), cap, err);
     }
     if (err) atomicOr(&h->status, err);
 }

@@ -29,7 +29,7 @@ def _fields_tiny():
     return out
 
 
-@pytest.mark.parametrize("variant", ["paper", "prelink", "basins", "tiles", "tile_trees"])
+@pytest.mark.parametrize("variant", ["paper", "prelink", "basins", "tiles", "tile_trees", "tile_trees_lowest"])
 def test_interleavings_reach_oracle(variant):
     for i, f in enumerate(_fields_tiny()):
         want = oracle.merge_tree(f)
@@ -78,7 +78,7 @@ def test_prelink_is_a_reachable_state():
     assert T == [(u, int(w[u])) if w[u] != u else (u, u) for u in range(f.size)]
 
 
-@pytest.mark.parametrize("variant", ["tiles", "tile_trees"])
+@pytest.mark.parametrize("variant", ["tiles", "tile_trees", "tile_trees_lowest"])
 @pytest.mark.parametrize("box", [(1, 1, 1), (2, 2, 2), (3, 2, 1), (4, 4, 4)])
 def test_two_level_boxes(box, variant):
     rng = np.random.default_rng(9)

@@ -41,6 +41,10 @@ Variants used by the GPU design, each checked to give the same unique T:
   between box-local minima, then those minima repaired); afterwards the
   edges that cross box faces are merged between the box-local minima of
   their ends, and a final repair runs over all vertices.
+- ``tile_trees_lowest``: as tile_trees, but of all edges joining the same two
+  basins only the one with the lowest upper end is merged (inside a box, and
+  across each box face): a connection at a lower level implies the same
+  connection at every higher one, so the others add nothing.
 """
 from __future__ import annotations
 
@@ -202,7 +206,7 @@ def simulate(f, seed=0, variant="paper", edge_order=None, serial=False,
         for a, b in edges:
             hi, lo = (a, b) if key(b) < key(a) else (b, a)
             merges.append((hi, hi, lo))
-    elif variant == "tile_trees":
+    elif variant in ("tile_trees", "tile_trees_lowest"):
         bx = _box_of(shape, box[: len(shape)])
         nb = neighbours(shape)
         zl = np.arange(N)
@@ -223,12 +227,25 @@ def simulate(f, seed=0, variant="paper", edge_order=None, serial=False,
             if zl[u] != u:
                 T[u] = (u, int(zl[u]))
         local = {}
+        lowest = {}
         for a, b in edges:
             hi = a if key(b) < key(a) else b
             m = (int(zl[a]), hi, int(zl[b]))
+            if variant == "tile_trees_lowest":
+                if zl[a] == zl[b]:
+                    continue
+                pair = (min(m[0], m[2]), max(m[0], m[2]))
+                if pair not in lowest or key(hi) < key(lowest[pair][1]):
+                    lowest[pair] = m
+                continue
             if bx[a] == bx[b]:
                 if zl[a] != zl[b]:
                     local.setdefault(int(bx[a]), []).append(m)
+            else:
+                merges.append(m)
+        for pair, m in lowest.items():
+            if bx[m[0]] == bx[m[2]]:
+                local.setdefault(int(bx[m[0]]), []).append(m)
             else:
                 merges.append(m)
         boxes = list(local.items())
