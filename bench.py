@@ -29,7 +29,7 @@ if ROOT not in sys.path:
 import numpy as np  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
-SRC = os.path.join(ROOT, "paper_2301_10838_amd", "csrc", "mt.hip")
+SRCS = [os.path.join(ROOT, "paper_2301_10838_amd", "csrc", n) for n in ("mt.hip", "mt_device.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 # Compulsory HBM bytes each kernel must move, per vertex of its launch (plus
@@ -58,8 +58,12 @@ def algo_bytes(kernel: str, n_vertices: int, n_pairs: int, n_local_minima: int) 
 
 
 def src_hash() -> str:
-    with open(SRC, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()
+    """SHA-256 over the kernel sources (host + device)."""
+    h = hashlib.sha256()
+    for p in SRCS:
+        with open(p, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def stored_traffic(kernel: str, workload: str):
@@ -248,6 +252,73 @@ def bench_backward(dev, mt, steps: int = 20):
     }
 
 
+def summarize_profiles(trace_dir: str, fetch_dir: str, write_dir: str, workload: str, command: str):
+    """Turn rocprofv3 CSV output (kernel trace + two counter passes) into the
+    committed summaries: profiles/<kernel table>.md and profiles/traffic.json.
+
+    HBM traffic per launch = counter reading scaled by what the same counter
+    reads for the plain 1 GiB copy of --calibrate-copy (bytes moved / reading).
+    """
+    import csv
+    import glob
+
+    def rows(d, name):
+        path = glob.glob(os.path.join(d, "**", f"*{name}"), recursive=True)
+        if not path:
+            raise FileNotFoundError(f"no {name} under {d}")
+        with open(path[0]) as fh:
+            return list(csv.DictReader(fh))
+
+    stats = rows(trace_dir, "kernel_stats.csv")
+    counters, peak = {}, {}
+    for d, cname in ((fetch_dir, "FETCH_SIZE"), (write_dir, "WRITE_SIZE")):
+        per = {}
+        for r in rows(d, "counter_collection.csv"):
+            if r["Counter_Name"] != cname:
+                continue
+            per.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]) * 1024.0)  # KiB -> bytes
+        counters[cname] = {k: sum(v) / len(v) for k, v in per.items()}
+        peak[cname] = {k: max(v) for k, v in per.items()}
+    # the calibration copy is the largest dispatch of torch's elementwise kernel
+    copy_name = next((k for k in counters["FETCH_SIZE"] if "elementwise" in k.lower()), None)
+    calib = 1 << 30
+    f_fac = calib / peak["FETCH_SIZE"][copy_name] if copy_name else None
+    w_fac = calib / peak["WRITE_SIZE"][copy_name] if copy_name else None
+    kernels = {}
+    for k in set(counters["FETCH_SIZE"]) & set(counters["WRITE_SIZE"]):
+        if not k.startswith("k_"):
+            continue
+        kernels[k] = {
+            "fetch_bytes": counters["FETCH_SIZE"][k] * (f_fac or 1.0),
+            "write_bytes": counters["WRITE_SIZE"][k] * (w_fac or 1.0),
+            "fetch_raw_kib": counters["FETCH_SIZE"][k] / 1024.0,
+            "write_raw_kib": counters["WRITE_SIZE"][k] / 1024.0,
+        }
+    traffic = {"workload": workload, "src_sha256": src_hash(), "copy_kernel": copy_name,
+               "fetch_scale": f_fac, "write_scale": w_fac, "kernels": kernels,
+               "command": command}
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(traffic, fh, indent=1, sort_keys=True)
+    lines = [f"# rocprofv3 kernel summary: {workload}", "", "Command (run from /tmp with TMPDIR=/tmp):", "",
+             "```", command, "```", "",
+             "| Kernel | Calls | Avg ms | Total % | HBM read MB/launch | HBM write MB/launch |",
+             "|---|---|---|---|---|---|"]
+    for r in stats:
+        k = r["Name"]
+        t = kernels.get(k, {})
+        rd = f"{t['fetch_bytes'] / 1e6:.1f}" if t else "-"
+        wr = f"{t['write_bytes'] / 1e6:.1f}" if t else "-"
+        lines.append(f"| {k} | {r['Calls']} | {float(r['AverageNs']) / 1e6:.3f} | {float(r['Percentage']):.1f} | "
+                     f"{rd} | {wr} |")
+    lines += ["", f"Counter scale from the plain copy kernel `{copy_name}` (1 GiB read, 1 GiB written): "
+              f"FETCH x{f_fac:.3f}, WRITE x{w_fac:.3f}." if copy_name else "", ""]
+    out = os.path.join(ROOT, "profiles", f"kernels_{workload}.md")
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines))
+    print(out, TRAFFIC_FILE)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -258,7 +329,13 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (3 times), the reference for HBM counters")
+    ap.add_argument("--summarize-profiles", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
+                    help="write profiles/ summaries from rocprofv3 CSV output and exit (no GPU)")
+    ap.add_argument("--profile-command", default="", help="command line recorded in the summary")
     args = ap.parse_args()
+    if args.summarize_profiles:
+        summarize_profiles(*args.summarize_profiles, args.workload, args.profile_command)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU: the merge-tree path here runs on a single MI355X and has no "
@@ -333,7 +410,7 @@ def main():
         src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
         for _ in range(3):
-            dst.copy_(src)
+            torch.mul(src, 1.0, out=dst)  # one elementwise kernel: 1 GiB read, 1 GiB written
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = {"read": src.numel() * 4, "write": dst.numel() * 4}
         del src, dst
