@@ -131,12 +131,24 @@ __device__ __forceinline__ void st_relaxed(T *p, T v)
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
 }
 
-// Key of the saddle s of slot x: the cached key if it belongs to s.
-__device__ __forceinline__ uint64_t saddle_key(Slot *__restrict__ S, const float *__restrict__ f, uint32_t x,
-                                               uint32_t s)
+// Both words of a slot, read together (two independent loads, one trip).
+struct SlotRead {
+    uint64_t w, k;
+};
+__device__ __forceinline__ SlotRead ld_slot(Slot *__restrict__ S, uint32_t x)
 {
-    const uint64_t k = ld_relaxed(&S[x].k);
-    return lo32(k) == s ? k : vkey(f, s);
+    SlotRead r;
+    r.w = ld_relaxed(&S[x].w);
+    r.k = ld_relaxed(&S[x].k);
+    return r;
+}
+
+// Key of the saddle of a slot read: the cached key if it belongs to that
+// saddle, else the value read from the field.
+__device__ __forceinline__ uint64_t saddle_key(const SlotRead &r, const float *__restrict__ f)
+{
+    const uint32_t s = lo32(r.w);
+    return lo32(r.k) == s ? r.k : vkey(f, s);
 }
 
 template <typename I>
@@ -482,9 +494,23 @@ __global__ __launch_bounds__(S::NT) void k_local(const float *__restrict__ f, ui
         slot[b0 + i].k = ((uint64_t)hk[sp] << 32) | sg;
         mkey[b0 + i] = ((uint64_t)hk[mp] << 32) | gid((int)mp);
     }
+    // Every vertex is labelled with the representative of its local basin
+    // at its own level (the deepest vertex it is connected to inside the tile
+    // at that level).  Later merges and chases start there: the links below
+    // the vertex's level are already followed.
     for (int p = threadIdx.x; p < VOL; p += NT) {
         const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
-        if (valid(lx, ly, lz)) lbl[gid(p)] = b0 + zl[p];
+        if (!valid(lx, ly, lz)) continue;
+        uint32_t x = zl[p];
+        const uint64_t level = tkey(hk, p);
+        for (uint32_t step = 0; step < cap; ++step) {
+            const uint32_t t = TL[x];
+            const uint32_t v = t >> 16;
+            if (v >= cnt) { err |= ST_CORRUPT; break; }
+            if (v == x || tkey(hk, t & 0xffffu) > level) break;
+            x = v;
+        }
+        lbl[gid(p)] = b0 + x;
     }
     if (err) atomicOr(&h->status, err);
 }
@@ -496,37 +522,33 @@ __device__ void gmerge(Slot *__restrict__ S, const uint64_t *__restrict__ mkey, 
                        uint32_t M, uint32_t n, uint32_t u, uint32_t s, uint64_t ks, uint32_t v, uint32_t cap,
                        uint32_t &err)
 {
-    uint64_t tu = ld_relaxed(&S[u].w);
-    uint64_t tv = ld_relaxed(&S[v].w);
+    SlotRead tu = ld_slot(S, u);
+    SlotRead tv = ld_slot(S, v);
     for (uint32_t step = 0; step < cap; ++step) {
-        const uint32_t u1 = hi32(tu), su = lo32(tu), v1 = hi32(tv), sv = lo32(tv);
+        const uint32_t u1 = hi32(tu.w), su = lo32(tu.w), v1 = hi32(tv.w), sv = lo32(tv.w);
         if (u1 >= M || v1 >= M || su >= n || sv >= n) { err |= ST_CORRUPT; return; }
-        if (u1 != u && saddle_key(S, f, u, su) < ks) { u = u1; tu = ld_relaxed(&S[u].w); continue; }
-        uint64_t kv = 0;
-        if (v1 != v) {
-            kv = saddle_key(S, f, v, sv);
-            if (kv < ks) { v = v1; tv = ld_relaxed(&S[v].w); continue; }
-        }
+        if (u1 != u && saddle_key(tu, f) < ks) { u = u1; tu = ld_slot(S, u); continue; }
+        if (v1 != v && saddle_key(tv, f) < ks) { v = v1; tv = ld_slot(S, v); continue; }
         if (u == v) return;
         if (mkey[v] < mkey[u]) {  // the upper minimum is re-pointed
             const uint32_t w = u; u = v; v = w;
-            const uint64_t tw = tu; tu = tv; tv = tw;
-            const uint32_t s1 = lo32(tv);
-            kv = (hi32(tv) != v) ? saddle_key(S, f, v, s1) : 0;
+            const SlotRead tw = tu; tu = tv; tv = tw;
         }
-        uint64_t seen = tv;
+        uint64_t seen = tv.w;
         if (__hip_atomic_compare_exchange_strong(&S[v].w, &seen, pack(s, u), __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                                  __HIP_MEMORY_SCOPE_AGENT)) {
             st_relaxed(&S[v].k, ks);
-            if (hi32(tv) == v) return;  // v was a root
-            s = lo32(tv);               // merge the displaced triplet again
+            if (hi32(tv.w) == v) return;  // v was a root
+            const uint64_t kv = saddle_key(tv, f);  // merge the displaced triplet again
+            s = lo32(tv.w);
             ks = kv;
-            v = hi32(tv);
-            tv = ld_relaxed(&S[v].w);
+            v = hi32(tv.w);
+            tv = ld_slot(S, v);
         } else {
-            tv = seen;
+            tv.w = seen;
+            tv.k = ld_relaxed(&S[v].k);
         }
-        tu = ld_relaxed(&S[u].w);
+        tu = ld_slot(S, u);
     }
     err |= ST_LIVELOCK;
 }
@@ -623,11 +645,11 @@ __device__ __forceinline__ uint32_t chase(Slot *__restrict__ S, const float *__r
                                           uint32_t x, uint64_t level, uint32_t cap, uint32_t &err)
 {
     for (uint32_t step = 0; step < cap; ++step) {
-        const uint64_t t = ld_relaxed(&S[x].w);
-        const uint32_t v = hi32(t), s = lo32(t);
+        const SlotRead t = ld_slot(S, x);
+        const uint32_t v = hi32(t.w), s = lo32(t.w);
         if (v >= M || s >= n) { err |= ST_CORRUPT; return x; }
         if (v == x) return x;
-        if (saddle_key(S, f, x, s) > level) return x;
+        if (saddle_key(t, f) > level) return x;
         x = v;
     }
     err |= ST_LIVELOCK;
@@ -640,11 +662,11 @@ __global__ __launch_bounds__(kBlock) void k_repair_min(const float *__restrict__
     const uint32_t M = h->n_minima;
     uint32_t err = 0;
     for (uint32_t m = blockIdx.x * kBlock + threadIdx.x; m < M; m += gridDim.x * kBlock) {
-        const uint64_t t = ld_relaxed(&S[m].w);
-        const uint32_t v = hi32(t), s = lo32(t);
+        const SlotRead t = ld_slot(S, m);
+        const uint32_t v = hi32(t.w), s = lo32(t.w);
         if (v == m) continue;
         if (v >= M || s >= n) { err |= ST_CORRUPT; continue; }
-        const uint32_t r = chase(S, f, M, n, v, saddle_key(S, f, m, s), cap, err);
+        const uint32_t r = chase(S, f, M, n, v, saddle_key(t, f), cap, err);
         if (r != v) st_relaxed(&S[m].w, pack(s, r));
     }
     if (err) atomicOr(&h->status, err);
