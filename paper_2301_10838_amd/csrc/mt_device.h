@@ -299,7 +299,7 @@ __device__ void lds_merge(uint32_t *TL, const uint32_t *hk, const uint16_t *mh, 
 }
 
 template <class S>
-__global__ __launch_bounds__(S::NT) void k_local(const float *__restrict__ f, uint32_t *__restrict__ lbl,
+__global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f, uint32_t *__restrict__ lbl,
                                                  Slot *__restrict__ slot, uint64_t *__restrict__ mkey,
                                                  const FieldDesc *__restrict__ D, const int32_t *__restrict__ tfield,
                                                  const int64_t *__restrict__ tstart, int nfc, int64_t tile0,
@@ -424,40 +424,56 @@ __global__ __launch_bounds__(S::NT) void k_local(const float *__restrict__ f, ui
     // is merged: the connection it makes at its level implies the connection
     // every other one would make at a higher level.  A table keyed by the
     // basin pair keeps that lowest edge; an edge that finds no table room is
-    // merged directly.
+    // merged directly.  Before touching the table, an edge is dropped when the
+    // edge of the same direction one step back in x (or y) joins the same two
+    // basins at a level no higher: "dominated" is a strict order, so the
+    // lowest edge of every pair always reaches the table.
     uint32_t err = 0;
-    for (int p = threadIdx.x; p < VOL; p += NT) {
-        const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
-        if (!valid(lx, ly, lz)) continue;
-        const uint32_t za = zl[p];
-        const uint64_t ka = tkey(hk, p);
-#define MT_EDGE(cond, q)                                                                    \
-        if (cond) {                                                                         \
-            const uint32_t zb = zl[(q)];                                                   \
-            if (zb != za) {                                                                \
-                const uint64_t kb = tkey(hk, (q));                                         \
-                const uint64_t ks = kb < ka ? ka : kb;                                     \
-                const uint32_t key = min(za, zb) | (max(za, zb) << 16);                   \
-                uint32_t slot_i = (key * 0x9E3779B1u) >> (32 - __builtin_ctz(H));          \
-                bool placed = false;                                                       \
-                for (int probe = 0; probe < 32; ++probe) {                                 \
-                    uint32_t prev = 0xffffffffu;                                           \
-                    __hip_atomic_compare_exchange_strong(hpair + slot_i, &prev, key,       \
-                        __ATOMIC_RELAXED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); \
-                    if (prev == 0xffffffffu || prev == key) {                              \
-                        atomicMin((unsigned long long *)(hbest + slot_i), (unsigned long long)ks); \
-                        placed = true;                                                     \
-                        break;                                                             \
-                    }                                                                      \
-                    slot_i = (slot_i + 1) & (H - 1);                                       \
-                }                                                                          \
-                if (!placed) lds_merge<HALF>(TL, hk, mh, za, (uint32_t)lo32(ks), zb, cap, err); \
-            }                                                                              \
+    const int lane = threadIdx.x & 63;
+    auto insert = [&](uint32_t key, uint64_t ks, uint32_t za, uint32_t zb) {
+        uint32_t si = (key * 0x9E3779B1u) >> (32 - __builtin_ctz(H));
+        for (int probe = 0; probe < 32; ++probe) {
+            uint32_t prev = 0xffffffffu;
+            __hip_atomic_compare_exchange_strong(hpair + si, &prev, key, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (prev == 0xffffffffu || prev == key) {
+                atomicMin((unsigned long long *)(hbest + si), (unsigned long long)ks);
+                return;
+            }
+            si = (si + 1) & (H - 1);
         }
-        MT_EDGE(lx + 1 < c.ex, p + 1)
-        MT_EDGE(ly + 1 < c.ey, p + TX)
-        MT_EDGE(lz + 1 < c.ez, p + TX * TY)
-#undef MT_EDGE
+        lds_merge<HALF>(TL, hk, mh, za, (uint32_t)lo32(ks), zb, cap, err);
+    };
+    for (int p = threadIdx.x; p < VOL; p += NT) {  // same trip count in every lane (VOL % NT == 0)
+        const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
+        const bool ok = valid(lx, ly, lz);
+        const uint32_t za = ok ? zl[p] : 0u;
+        const uint64_t ka = ok ? tkey(hk, p) : 0ull;
+#pragma unroll
+        for (int dir = 0; dir < 3; ++dir) {
+            const int q = p + (dir == 0 ? 1 : dir == 1 ? TX : TX * TY);
+            const bool edge = ok && (dir == 0 ? lx + 1 < c.ex : dir == 1 ? ly + 1 < c.ey : lz + 1 < c.ez);
+            uint32_t key = 0xffffffffu, zb = 0;
+            uint64_t ks = ~0ull;
+            if (edge) {
+                zb = zl[q];
+                if (zb != za) {
+                    const uint64_t kb = tkey(hk, q);
+                    ks = kb < ka ? ka : kb;
+                    key = min(za, zb) | (max(za, zb) << 16);
+                }
+            }
+            const uint32_t key1 = __shfl_up(key, 1);
+            const uint64_t ks1 = ((uint64_t)__shfl_up((uint32_t)(ks >> 32), 1) << 32) | __shfl_up((uint32_t)ks, 1);
+            bool dom = lane >= 1 && lx > 0 && key1 == key && ks1 <= ks;
+            if (TX < 64) {
+                const uint32_t key2 = __shfl_up(key, TX);
+                const uint64_t ks2 =
+                    ((uint64_t)__shfl_up((uint32_t)(ks >> 32), TX) << 32) | __shfl_up((uint32_t)ks, TX);
+                dom = dom || (lane >= TX && ly > 0 && key2 == key && ks2 <= ks);
+            }
+            if (key != 0xffffffffu && !dom) insert(key, ks, za, zb);
+        }
     }
     __syncthreads();
     for (int i = threadIdx.x; i < H; i += NT) {
