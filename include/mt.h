@@ -198,6 +198,36 @@ int mt_profile_end(void);
 int mt_profile_count(void);
 int mt_profile_get(int i, char *name, size_t name_len, double *total_ms, int64_t *launches);
 
+/*
+ * Tile shapes and their autotuner.  The stencil passes cut every field into
+ * tiles of one of a few compiled shapes, chosen per dims class (0: 3-D
+ * fields, nz > 1; 1: 2-D, nz == 1 < ny; 2: 1-D).  The output never depends on
+ * the shape; the speed does.
+ *
+ * mt_tile_shape_count / mt_tile_shape_info enumerate the compiled shapes
+ * (tile extents, workgroup threads, dims class).  mt_set_tile_shape selects
+ * shape `id` for its class (process-wide; later calls and newly captured
+ * batch graphs use it); mt_get_tile_shape returns the current id.
+ *
+ * mt_autotune runs the build of the given batch (host dims, device fields as
+ * for mt_batch_build) once per candidate shape of every class present,
+ * `reps` timed repetitions each with HIP events on `stream`, checks that
+ * every candidate writes bit-identical triplets (else MT_ERR_INTERNAL), and
+ * selects the fastest shape per class.  triplets and triplets_check are two
+ * device buffers of uint32[N][2]; workspace must hold
+ * mt_autotune_workspace_bytes(dims, n_fields) bytes (candidates that need
+ * more than ws_bytes are skipped).  best_ms (host, may be NULL) receives the
+ * best time per class, -1 for classes not present.  Synchronizes.
+ */
+int mt_tile_shape_count(void);
+int mt_tile_shape_info(int id, int *tx, int *ty, int *tz, int *threads, int *dims_class);
+int mt_set_tile_shape(int dims_class, int id);
+int mt_get_tile_shape(int dims_class);
+size_t mt_autotune_workspace_bytes(const int64_t *dims, int32_t n_fields);
+int mt_autotune(const float *fields, const int64_t *dims, int32_t n_fields, uint32_t *triplets,
+                uint32_t *triplets_check, void *workspace, size_t ws_bytes, int reps, void *stream,
+                double *best_ms);
+
 /* Free cached graph plans (device and host memory they hold).  Not safe to
  * call while another thread is inside the library. */
 void mt_release_caches(void);

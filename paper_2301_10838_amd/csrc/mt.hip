@@ -63,7 +63,7 @@ static void with_shape(int id, F &&fn)
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t D, tfield, tstart, cs, pcnt, lbl, slot, mkey, total;
+    size_t D, tfield, tstart, cs, pcnt, lbl, slot, mkey, queue, total;
 };
 
 struct ClassLaunch {
@@ -75,7 +75,7 @@ struct ClassLaunch {
 
 struct Plan {
     std::vector<FieldDesc> d;  // field order
-    int64_t n_total = 0, n_tiles = 0, n_chunks = 0, m_cap = 0;
+    int64_t n_total = 0, n_tiles = 0, n_chunks = 0, m_cap = 0, q_cap = 0;
     ClassLaunch cls[3];
     Layout lay{};
 };
@@ -116,16 +116,17 @@ static void read_env_locked()
 
 static int field_class(int64_t ny, int64_t nz) { return nz > 1 ? 0 : (ny > 1 ? 1 : 2); }
 
-static int make_plan(const int64_t *dims, int32_t nf, Plan &p)
+static int make_plan(const int64_t *dims, int32_t nf, Plan &p, const int *shape_override = nullptr)
 {
     if (!dims || nf < 1) return MT_ERR_INVALID_ARG;
     int shape[3];
     {
         std::lock_guard<std::mutex> lk(g_cfg_mu);
         read_env_locked();
-        for (int c = 0; c < 3; ++c) shape[c] = g_shape[c];
+        for (int c = 0; c < 3; ++c) shape[c] = shape_override ? shape_override[c] : g_shape[c];
     }
     p.d.assign(nf, FieldDesc{});
+    p.q_cap = 0;
     int64_t off = 0, chunks = 0, mcap = 0;
     for (int32_t i = 0; i < nf; ++i) {
         const int64_t nx = dims[3 * i], ny = dims[3 * i + 1], nz = dims[3 * i + 2];
@@ -153,6 +154,9 @@ static int make_plan(const int64_t *dims, int32_t nf, Plan &p)
         cl.cb = pos;
         cl.tile0 = tiles;
         const ShapeInfo &sh = kShapes[shape[c]];
+        // face edges a tile of this shape can own (+x always, +y and +z when the shape spans them)
+        const int64_t faces = (int64_t)sh.ty * sh.tz + (sh.ty > 1 ? (int64_t)sh.tx * sh.tz : 0) +
+                              (sh.tz > 1 ? (int64_t)sh.tx * sh.ty : 0);
         for (int32_t i = 0; i < nf; ++i) {
             FieldDesc &d = p.d[i];
             if (field_class(d.ny, d.nz) != c) continue;
@@ -165,9 +169,12 @@ static int make_plan(const int64_t *dims, int32_t nf, Plan &p)
         }
         cl.nfc = pos - cl.cb;
         cl.ntiles = tiles - cl.tile0;
+        // one queue per XCD; a workgroup of this class launch serves at most
+        // ceil(ntiles / 8) tiles of each queue
+        p.q_cap += (cl.ntiles + 7) / 8 * faces;
     }
     mcap += tiles;
-    if (mcap >= (1LL << 31)) return MT_ERR_TOO_LARGE;
+    if (mcap >= (1LL << 31) || p.q_cap >= (1LL << 31)) return MT_ERR_TOO_LARGE;
     p.n_total = off;
     p.n_tiles = tiles;
     p.n_chunks = chunks;
@@ -182,6 +189,7 @@ static int make_plan(const int64_t *dims, int32_t nf, Plan &p)
     L.lbl = o; o = align256(o + sizeof(uint32_t) * off);
     L.slot = o; o = align256(o + sizeof(Slot) * mcap);
     L.mkey = o; o = align256(o + sizeof(uint64_t) * mcap);
+    L.queue = o; o = align256(o + sizeof(Fact) * p.q_cap * 8);
     L.total = o;
     return MT_OK;
 }
@@ -194,6 +202,7 @@ struct Ptrs {
     uint32_t *pcnt, *lbl;
     Slot *slot;
     uint64_t *mkey;
+    Fact *queue;
 };
 
 static Ptrs ws_ptrs(const Plan &p, void *ws)
@@ -210,6 +219,7 @@ static Ptrs ws_ptrs(const Plan &p, void *ws)
     w.lbl = (uint32_t *)(b + L.lbl);
     w.slot = (Slot *)(b + L.slot);
     w.mkey = (uint64_t *)(b + L.mkey);
+    w.queue = (Fact *)(b + L.queue);
     return w;
 }
 
@@ -309,9 +319,9 @@ template <class S>
 static int launch_cross(const Plan &p, const ClassLaunch &cl, const Ptrs &w, const float *f, hipStream_t st)
 {
     MT_LAUNCH("k_cross", HIP_KERNEL_NAME(k_cross<S>), dim3((unsigned)cl.ntiles), dim3(S::NT), st, f,
-              (const uint32_t *)w.lbl, w.slot, (const uint64_t *)w.mkey, (const FieldDesc *)w.D,
+              (const uint32_t *)w.lbl, w.queue, (uint32_t)p.q_cap, (const FieldDesc *)w.D,
               (const int32_t *)w.tfield + cl.cb, (const int64_t *)w.tstart + cl.cb, cl.nfc, cl.tile0, cl.ntiles,
-              g_remap, (uint32_t)p.n_total, g_cap, w.h);
+              g_remap, w.h);
     return MT_OK;
 }
 
@@ -334,6 +344,9 @@ static int enqueue_build(const Plan &p, const Ptrs &w, const float *f, uint64_t 
         with_shape(cl.shape, [&](auto s) { rc = launch_cross<decltype(s)>(p, cl, w, f, st); });
         if (rc != MT_OK) return rc;
     }
+    const unsigned gq = 8 * (unsigned)std::min<int64_t>(2048, std::max<int64_t>(1, (p.q_cap + kBlock - 1) / kBlock));
+    MT_LAUNCH("k_merge_q", k_merge_q, dim3(gq), dim3(kBlock), st, f, (const Fact *)w.queue, (uint32_t)p.q_cap, w.slot,
+              (const uint64_t *)w.mkey, n, g_cap, w.h);
     const unsigned gm = (unsigned)std::min<int64_t>(8192, std::max<int64_t>(1, (p.m_cap + kBlock - 1) / kBlock));
     MT_LAUNCH("k_repair_min", k_repair_min, dim3(gm), dim3(kBlock), st, f, w.slot, n, g_cap, w.h);
     MT_LAUNCH("k_repair_reg", k_repair_reg, dim3((unsigned)p.n_chunks), dim3(kBlock), st, f,
@@ -357,6 +370,16 @@ static int enqueue_pairs(const Plan &p, const Ptrs &w, bool count, const float *
               (const FieldDesc *)w.D, (const int64_t *)w.cs, nf, (const uint32_t *)w.pcnt, capacity, birth, death,
               bval, dval);
     return MT_OK;
+}
+
+// Any difference between two triplet arrays latches ST_CORRUPT (autotuner check).
+__global__ void k_compare(const uint64_t *__restrict__ a, const uint64_t *__restrict__ b, int64_t n,
+                          uint32_t *__restrict__ status)
+{
+    bool diff = false;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        diff |= a[i] != b[i];
+    if (__ballot(diff) != 0ull && (threadIdx.x & 63) == 0) atomicOr(status, ST_CORRUPT);
 }
 
 static int status_to_code(uint32_t s)
@@ -546,6 +569,121 @@ int mt_sync_status(const void *workspace, void *stream, int64_t *n_pairs, int64_
     if (n_pairs) *n_pairs = h.total_pairs;
     if (n_roots) *n_roots = h.roots;
     return status_to_code(h.status);
+}
+
+int mt_tile_shape_count(void) { return kNumShapes; }
+
+int mt_tile_shape_info(int id, int *tx, int *ty, int *tz, int *threads, int *dims_class)
+{
+    if (id < 0 || id >= kNumShapes) return MT_ERR_INVALID_ARG;
+    const ShapeInfo &s = kShapes[id];
+    if (tx) *tx = s.tx;
+    if (ty) *ty = s.ty;
+    if (tz) *tz = s.tz;
+    if (threads) *threads = s.nt;
+    if (dims_class) *dims_class = s.cls;
+    return MT_OK;
+}
+
+int mt_set_tile_shape(int dims_class, int id)
+{
+    if (dims_class < 0 || dims_class > 2 || id < 0 || id >= kNumShapes || kShapes[id].cls != dims_class)
+        return MT_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(g_cfg_mu);
+    read_env_locked();
+    g_shape[dims_class] = id;
+    return MT_OK;
+}
+
+int mt_get_tile_shape(int dims_class)
+{
+    if (dims_class < 0 || dims_class > 2) return MT_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(g_cfg_mu);
+    read_env_locked();
+    return g_shape[dims_class];
+}
+
+size_t mt_autotune_workspace_bytes(const int64_t *dims, int32_t n_fields)
+{
+    size_t best = 0;
+    for (int a = 0; a < kNumShapes; ++a) {
+        if (kShapes[a].cls != 0) continue;
+        for (int b = 0; b < kNumShapes; ++b) {
+            if (kShapes[b].cls != 1) continue;
+            for (int c = 0; c < kNumShapes; ++c) {
+                if (kShapes[c].cls != 2) continue;
+                const int sh[3] = {a, b, c};
+                Plan p;
+                if (make_plan(dims, n_fields, p, sh) != MT_OK) return 0;
+                best = std::max(best, p.lay.total);
+            }
+        }
+    }
+    return best;
+}
+
+int mt_autotune(const float *fields, const int64_t *dims, int32_t n_fields, uint32_t *triplets,
+                uint32_t *triplets_check, void *workspace, size_t ws_bytes, int reps, void *stream,
+                double *best_ms)
+{
+    if (!fields || !triplets || !triplets_check || reps < 1) return MT_ERR_INVALID_ARG;
+    if (((uintptr_t)triplets & 7u) || ((uintptr_t)triplets_check & 7u)) return MT_ERR_INVALID_ARG;
+    Plan p0;
+    int rc = make_plan(dims, n_fields, p0);
+    if (rc != MT_OK) return rc;
+    if ((rc = check_ws(p0, workspace, ws_bytes)) != MT_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return MT_ERR_HIP;
+    int shape[3];
+    for (int c = 0; c < 3; ++c) shape[c] = mt_get_tile_shape(c);
+    bool have_ref = false;
+    rc = MT_OK;
+    for (int c = 0; c < 3 && rc == MT_OK; ++c) {
+        if (best_ms) best_ms[c] = -1.0;
+        if (p0.cls[c].ntiles == 0) continue;
+        int best_id = shape[c];
+        double best_t = 1e300;
+        for (int id = 0; id < kNumShapes && rc == MT_OK; ++id) {
+            if (kShapes[id].cls != c) continue;
+            int sh[3] = {shape[0], shape[1], shape[2]};
+            sh[c] = id;
+            Plan p;
+            if ((rc = make_plan(dims, n_fields, p, sh)) != MT_OK) break;
+            if (p.lay.total > ws_bytes) continue;  // does not fit the caller's workspace
+            const Ptrs w = ws_ptrs(p, workspace);
+            uint64_t *out = (uint64_t *)(have_ref ? triplets : triplets_check);
+            for (int r = -1; r < reps && rc == MT_OK; ++r) {  // r = -1: warm-up
+                if (r == 0 && hipEventRecord(e0, st) != hipSuccess) rc = MT_ERR_HIP;
+                if (rc == MT_OK) rc = enqueue_setup(p, w, ~0u, true, st);
+                if (rc == MT_OK) rc = enqueue_build(p, w, fields, out, st);
+            }
+            if (rc != MT_OK) break;
+            if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) { rc = MT_ERR_HIP; break; }
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rc = MT_ERR_HIP; break; }
+            if (have_ref) {  // same triplets as the first candidate, bit for bit
+                hipLaunchKernelGGL(k_compare, dim3(1024), dim3(kBlock), 0, st, (const uint64_t *)triplets,
+                                   (const uint64_t *)triplets_check, p.n_total, &w.h->status);
+            }
+            Header h;
+            if ((rc = read_header(workspace, st, h)) != MT_OK) break;
+            if ((rc = status_to_code(h.status)) != MT_OK) break;
+            have_ref = true;
+            if (ms / reps < best_t) {
+                best_t = ms / reps;
+                best_id = id;
+            }
+        }
+        if (rc == MT_OK) {
+            shape[c] = best_id;
+            mt_set_tile_shape(c, best_id);
+            if (best_ms) best_ms[c] = best_t;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
 }
 
 int mt_build_stats(const void *workspace, void *stream, int64_t *n_local_minima)

@@ -89,7 +89,15 @@ struct Header {
     uint32_t n_minima;       // minimum numbers handed out
     int64_t total_pairs;
     int64_t roots;
-    int64_t reserved[5];
+    uint32_t n_cross[8];     // cross-tile facts queued, per XCD
+    int64_t reserved[1];
+};
+
+// A fact "minima a and b are connected at the level of the saddle whose key
+// is ks", queued for the cross-tile merge.
+struct Fact {
+    uint32_t a, b;
+    uint64_t ks;
 };
 
 struct Slot {
@@ -246,6 +254,7 @@ __global__ void k_setup(SetupArgs a, FieldDesc *D, int32_t *tfield, int64_t *tst
             h->total_pairs = 0;
             h->roots = 0;
             h->n_minima = 0;
+            for (int x = 0; x < 8; ++x) h->n_cross[x] = 0;
         }
     }
 }
@@ -579,34 +588,43 @@ constexpr int pow2_at_least(int v)
 // Per tile: the edges leaving through its +x, +y, +z faces.  A local basin
 // lies inside one tile, so all edges joining the same two local basins cross
 // the same face and meet in this workgroup; only the lowest of them (smallest
-// upper end) is merged, the others add nothing above its level.
+// upper end) is kept, the others add nothing above its level.  The kept facts
+// are appended to the queue of the XCD this workgroup runs on (one atomic per
+// workgroup) and merged by k_merge_q, where every lane has a merge to do and
+// each XCD works on the facts of its own tiles (so its L2 holds their slots).
 template <class S>
 __global__ __launch_bounds__(S::NT) void k_cross(const float *__restrict__ f, const uint32_t *__restrict__ lbl,
-                                                 Slot *__restrict__ slot, const uint64_t *__restrict__ mkey,
+                                                 Fact *__restrict__ queue, uint32_t qsub,
                                                  const FieldDesc *__restrict__ D, const int32_t *__restrict__ tfield,
                                                  const int64_t *__restrict__ tstart, int nfc, int64_t tile0,
-                                                 int64_t ntiles, int remap, uint32_t n, uint32_t cap,
-                                                 Header *__restrict__ h)
+                                                 int64_t ntiles, int remap, Header *__restrict__ h)
 {
-    constexpr int TX = S::TX, TY = S::TY, TZ = S::TZ;
+    constexpr int TX = S::TX, TY = S::TY, TZ = S::TZ, NT = S::NT;
     // faces that can have a neighbour: a 2-D shape has no z face, a 1-D one no y face
     constexpr int FX = TY * TZ, FY = TY > 1 ? TX * TZ : 0, FZ = TZ > 1 ? TX * TY : 0;
-    constexpr int H = pow2_at_least(2 * (FX + FY + FZ)) < 2048 ? pow2_at_least(2 * (FX + FY + FZ)) : 2048;
+    constexpr int E = FX + FY + FZ;
+    constexpr int H = pow2_at_least(2 * E) < 2048 ? pow2_at_least(2 * E) : 2048;
     __shared__ uint64_t hpair[H];  // (lower number | higher number << 32)
     __shared__ uint64_t hbest[H];  // lowest upper-end key of an edge joining that pair
+    __shared__ uint32_t wsum[NT / 64];
+    __shared__ uint32_t sbase;
     const int64_t tl = xcd_tile(blockIdx.x, gridDim.x, remap);
     if (tl >= ntiles) return;
     const TileCtx c = tile_ctx<S>(D, tfield, tstart, nfc, tile0 + tl);
     const uint32_t off = (uint32_t)c.d.offset;
     const bool hx = c.x0 + TX < c.d.nx, hy = c.y0 + TY < c.d.ny, hz = c.z0 + TZ < c.d.nz;
     const uint32_t M = h->n_minima;
-    for (int i = threadIdx.x; i < H; i += S::NT) {
+    for (int i = threadIdx.x; i < H; i += NT) {
         hpair[i] = ~0ull;
         hbest[i] = ~0ull;
     }
     __syncthreads();
     uint32_t err = 0;
-    for (int e = threadIdx.x; e < FX + FY + FZ; e += S::NT) {
+    // facts that find no table room are queued as they are (at most one per edge)
+    constexpr int kOverflow = (E + NT - 1) / NT;
+    Fact over[kOverflow];
+    int nover = 0;
+    for (int e = threadIdx.x; e < E; e += NT) {
         int lx, ly, lz;
         int64_t step;
         bool ok;
@@ -640,14 +658,58 @@ __global__ __launch_bounds__(S::NT) void k_cross(const float *__restrict__ f, co
             }
             si = (si + 1) & (H - 1);
         }
-        if (!placed) gmerge(slot, mkey, f, M, n, za, lo32(ks), ks, zb, cap, err);
+        if (!placed) over[nover++] = Fact{za, zb, ks};
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < H; i += S::NT) {
+
+    // count this workgroup's facts, reserve queue room with one atomic
+    uint32_t mine = nover;
+    for (int i = threadIdx.x; i < H; i += NT) mine += hpair[i] != ~0ull;
+    uint32_t incl = mine;
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t v = __shfl_up(incl, o);
+        if ((threadIdx.x & 63) >= o) incl += v;
+    }
+    if ((threadIdx.x & 63) == 63) wsum[threadIdx.x >> 6] = incl;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t tot = 0;
+        for (int w = 0; w < NT / 64; ++w) tot += wsum[w];
+        sbase = tot ? atomicAdd(&h->n_cross[blockIdx.x % 8], tot) : 0u;
+    }
+    __syncthreads();
+    uint32_t pos = sbase + incl - mine;
+    for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) pos += wsum[w];
+    Fact *__restrict__ mq = queue + (size_t)(blockIdx.x % 8) * qsub;
+    auto put = [&](const Fact &q) {
+        if (pos < qsub) mq[pos] = q;
+        else err |= ST_CORRUPT;  // cannot happen: each queue holds every face edge of its tiles
+        ++pos;
+    };
+    for (int i = 0; i < nover; ++i) put(over[i]);
+    for (int i = threadIdx.x; i < H; i += NT) {
         const uint64_t key = hpair[i];
-        if (key == ~0ull) continue;
-        const uint64_t ks = hbest[i];
-        gmerge(slot, mkey, f, M, n, lo32(key), lo32(ks), ks, hi32(key), cap, err);
+        if (key != ~0ull) put(Fact{lo32(key), hi32(key), hbest[i]});
+    }
+    if (err) atomicOr(&h->status, err);
+}
+
+// Merge of the queued cross-tile facts, one per lane; workgroup b serves the
+// queue of XCD b % 8 (the grid is a multiple of 8 workgroups).
+__global__ __launch_bounds__(kBlock) void k_merge_q(const float *__restrict__ f, const Fact *__restrict__ queue,
+                                                    uint32_t qsub, Slot *__restrict__ slot,
+                                                    const uint64_t *__restrict__ mkey, uint32_t n, uint32_t cap,
+                                                    Header *__restrict__ h)
+{
+    const uint32_t M = h->n_minima;
+    const uint32_t x = blockIdx.x % 8, per = gridDim.x / 8;
+    const uint32_t Q = min(h->n_cross[x], qsub);
+    const Fact *__restrict__ mq = queue + (size_t)x * qsub;
+    uint32_t err = 0;
+    for (uint32_t i = (blockIdx.x / 8) * kBlock + threadIdx.x; i < Q; i += per * kBlock) {
+        const Fact q = mq[i];
+        if (q.a >= M || q.b >= M || lo32(q.ks) >= n) { err |= ST_CORRUPT; continue; }
+        gmerge(slot, mkey, f, M, n, q.a, lo32(q.ks), q.ks, q.b, cap, err);
     }
     if (err) atomicOr(&h->status, err);
 }

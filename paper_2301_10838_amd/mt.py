@@ -30,7 +30,8 @@ EXPORTS = [
     "mt_status_string", "mt_workspace_bytes", "mt_batch_workspace_bytes", "mt_build", "mt_persistence_pairs",
     "mt_batch_build", "mt_sync_status", "mt_build_stats", "mt_pairs_backward", "mt_release_caches",
     "mt_profile_begin",
-    "mt_profile_end", "mt_profile_count", "mt_profile_get",
+    "mt_profile_end", "mt_profile_count", "mt_profile_get", "mt_tile_shape_count", "mt_tile_shape_info",
+    "mt_set_tile_shape", "mt_get_tile_shape", "mt_autotune_workspace_bytes", "mt_autotune",
 ]
 
 
@@ -80,6 +81,18 @@ def load_library():
     lib.mt_profile_count.restype = ctypes.c_int
     lib.mt_profile_get.argtypes = [ctypes.c_int, ctypes.c_char_p, SZ, P, P]
     lib.mt_profile_get.restype = ctypes.c_int
+    lib.mt_tile_shape_count.argtypes = []
+    lib.mt_tile_shape_count.restype = ctypes.c_int
+    lib.mt_tile_shape_info.argtypes = [ctypes.c_int, P, P, P, P, P]
+    lib.mt_tile_shape_info.restype = ctypes.c_int
+    lib.mt_set_tile_shape.argtypes = [ctypes.c_int, ctypes.c_int]
+    lib.mt_set_tile_shape.restype = ctypes.c_int
+    lib.mt_get_tile_shape.argtypes = [ctypes.c_int]
+    lib.mt_get_tile_shape.restype = ctypes.c_int
+    lib.mt_autotune_workspace_bytes.argtypes = [P, I32]
+    lib.mt_autotune_workspace_bytes.restype = SZ
+    lib.mt_autotune.argtypes = [P, P, I32, P, P, P, SZ, ctypes.c_int, P, P]
+    lib.mt_autotune.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -317,6 +330,45 @@ def build_stats(workspace: torch.Tensor) -> int:
     _check(load_library().mt_build_stats(workspace.data_ptr(), _stream_ptr(workspace.device), ctypes.byref(n)),
            "mt_build_stats")
     return n.value
+
+
+def tile_shapes():
+    """Compiled tile shapes: list of dicts (id, tx, ty, tz, threads, dims_class)."""
+    lib = load_library()
+    out = []
+    for i in range(lib.mt_tile_shape_count()):
+        v = [ctypes.c_int(0) for _ in range(5)]
+        _check(lib.mt_tile_shape_info(i, *[ctypes.byref(x) for x in v]), "mt_tile_shape_info")
+        out.append(dict(id=i, tx=v[0].value, ty=v[1].value, tz=v[2].value, threads=v[3].value,
+                        dims_class=v[4].value))
+    return out
+
+
+def set_tile_shape(dims_class: int, shape_id: int):
+    _check(load_library().mt_set_tile_shape(dims_class, shape_id), "mt_set_tile_shape")
+
+
+def get_tile_shape(dims_class: int) -> int:
+    return int(load_library().mt_get_tile_shape(dims_class))
+
+
+def autotune(fields: Sequence[torch.Tensor], reps: int = 3):
+    """Time every compiled tile shape on this batch (bit-identical output is
+    checked by the library) and select the fastest per dims class.  Returns
+    {dims_class: (shape id, best ms)} for the classes present."""
+    lib = load_library()
+    dev = fields[0].device
+    dims = [grid_dims(f.shape) for f in fields]
+    dims_c = (ctypes.c_int64 * (3 * len(dims)))(*[v for d in dims for v in d])
+    flat = torch.cat([_field(f).reshape(-1) for f in fields])
+    n = flat.numel()
+    t1 = torch.empty((n, 2), dtype=torch.int32, device=dev)
+    t2 = torch.empty_like(t1)
+    ws = alloc_workspace(lib.mt_autotune_workspace_bytes(dims_c, len(dims)), dev)
+    best = (ctypes.c_double * 3)()
+    _check(lib.mt_autotune(flat.data_ptr(), dims_c, len(dims), t1.data_ptr(), t2.data_ptr(), ws.data_ptr(),
+                           ws.numel(), reps, _stream_ptr(dev), best), "mt_autotune")
+    return {c: (get_tile_shape(c), best[c]) for c in range(3) if best[c] >= 0}
 
 
 def release_caches():

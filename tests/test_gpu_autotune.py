@@ -1,0 +1,58 @@
+"""Autotuner: every candidate tile shape gives bit-identical triplets (checked
+inside the library), the chosen shapes are applied, and results stay exact."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import device, gpu_tree
+from paper_2301_10838_amd import fields
+
+pytestmark = pytest.mark.gpu
+
+
+def test_autotune_selects_and_stays_exact(dev=None, tmp_path=None):
+    import paper_2301_10838_amd.mt as mt
+
+    dev = device()
+    fs = [fields.lognormal_grf((40, 36, 33), 401), fields.lognormal_grf((150, 170), 402),
+          fields.uniform((3000,), 403)]
+    before = {c: mt.get_tile_shape(c) for c in range(3)}
+    try:
+        res = mt.autotune([torch.from_numpy(f).to(dev) for f in fs], reps=1)
+        assert set(res) == {0, 1, 2}
+        shapes = {s["id"]: s for s in mt.tile_shapes()}
+        for c, (sid, ms) in res.items():
+            assert shapes[sid]["dims_class"] == c and ms > 0
+            assert mt.get_tile_shape(c) == sid
+        for f in fs:
+            T, _ = gpu_tree(f, dev)
+            assert np.array_equal(T, oracle.merge_tree(f))
+        # every compiled shape, forced one by one, gives the oracle's tree
+        for s in mt.tile_shapes():
+            mt.set_tile_shape(s["dims_class"], s["id"])
+            f = fs[s["dims_class"]]
+            T, _ = gpu_tree(f, dev)
+            assert np.array_equal(T, oracle.merge_tree(f)), s
+    finally:
+        for c, sid in before.items():
+            mt.set_tile_shape(c, sid)
+
+
+def test_tune_driver_cache(tmp_path, monkeypatch):
+    import paper_2301_10838_amd.mt as mt
+    from paper_2301_10838_amd import tune
+
+    dev = device()
+    monkeypatch.setenv("MT_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
+    before = {c: mt.get_tile_shape(c) for c in range(3)}
+    try:
+        fs = [torch.from_numpy(fields.lognormal_grf((24, 20, 18), 404)).to(dev)]
+        first = tune.tune(fs, reps=1)
+        assert (tmp_path / "tune.json").exists()
+        mt.set_tile_shape(0, before[0])
+        again = tune.tune(fs, reps=1)  # from the cache
+        assert again == first
+    finally:
+        for c, sid in before.items():
+            mt.set_tile_shape(c, sid)
