@@ -38,6 +38,7 @@ constexpr ShapeInfo kShapes[] = {
     {16, 8, 8, 256, 0},   {32, 8, 4, 256, 0},   {8, 8, 8, 256, 0},     {16, 16, 4, 256, 0},
     {16, 16, 16, 1024, 0}, {32, 16, 8, 1024, 0}, {64, 16, 1, 256, 1},  {32, 32, 1, 256, 1},
     {64, 64, 1, 1024, 1}, {128, 32, 1, 1024, 1}, {1024, 1, 1, 256, 2}, {4096, 1, 1, 1024, 2},
+    {16, 16, 8, 512, 0},  {64, 32, 1, 512, 1},   {2048, 1, 1, 512, 2},
 };
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 
@@ -56,7 +57,10 @@ static void with_shape(int id, F &&fn)
     case 8: fn(Shape<64, 64, 1, 1024>{}); break;
     case 9: fn(Shape<128, 32, 1, 1024>{}); break;
     case 10: fn(Shape<1024, 1, 1, 256>{}); break;
-    default: fn(Shape<4096, 1, 1, 1024>{}); break;
+    case 11: fn(Shape<4096, 1, 1, 1024>{}); break;
+    case 12: fn(Shape<16, 16, 8, 512>{}); break;
+    case 13: fn(Shape<64, 32, 1, 512>{}); break;
+    default: fn(Shape<2048, 1, 1, 512>{}); break;
     }
 }
 

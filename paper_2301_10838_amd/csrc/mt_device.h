@@ -772,19 +772,26 @@ __global__ __launch_bounds__(kBlock) void k_repair_reg(const float *__restrict__
         const uint32_t u = off + (uint32_t)j;
         const uint32_t z = lbl[u];
         if (z >= M) { err |= ST_CORRUPT; continue; }
-        uint32_t s, r;
-        if (lo32(mkey[z]) == u) {  // u is a local minimum
-            const uint64_t t = S[z].w;
-            s = lo32(t);
-            r = hi32(t);
-            if (r >= M || s >= n) { err |= ST_CORRUPT; continue; }
-            np += (s != u);
-            nr += (r == z);
-        } else {
+        // everything that depends only on z, in one trip
+        const uint64_t mz = mkey[z];
+        const SlotRead t = ld_slot(S, z);
+        const uint32_t s0 = lo32(t.w), v0 = hi32(t.w);
+        if (v0 >= M || s0 >= n) { err |= ST_CORRUPT; continue; }
+        uint32_t s, gr;
+        if (lo32(mz) == u) {  // u is a local minimum: its own repaired triplet
+            s = s0;
+            np += (s0 != u);
+            nr += (v0 == z);
+            gr = v0 == z ? u : lo32(mkey[v0]);
+        } else {              // (u, u, representative of z at the level of u)
             s = u;
-            r = chase(S, f, M, n, z, vkey(f, u), cap, err);
+            const uint64_t level = vkey(f, u);
+            if (v0 == z || saddle_key(t, f) > level) {
+                gr = lo32(mz);
+            } else {
+                gr = lo32(mkey[chase(S, f, M, n, v0, level, cap, err)]);
+            }
         }
-        const uint32_t gr = lo32(mkey[r]);
         if (gr >= n) { err |= ST_CORRUPT; continue; }
         T[u] = pack(s - off, gr - off);
     }
