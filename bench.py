@@ -39,6 +39,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 ALGO_BYTES_PER_VERTEX = {
     "k_local": 8,        # read f, write the local-basin label
     "k_cross": 0,        # face edges only (per-minimum term below)
+    "k_merge_q": 0,      # per-fact and per-minimum terms below
     "k_repair_min": 0,   # per-minimum term below
     "k_repair_reg": 16,  # read label and f, write the triplet
     "k_pairs_count": 8,  # read the triplet
@@ -46,8 +47,10 @@ ALGO_BYTES_PER_VERTEX = {
 }
 
 
-def algo_bytes(kernel: str, n_vertices: int, n_pairs: int, n_local_minima: int) -> float:
+def algo_bytes(kernel: str, n_vertices: int, n_pairs: int, n_local_minima: int, n_facts: int = 0) -> float:
     b = ALGO_BYTES_PER_VERTEX[kernel] * n_vertices
+    if kernel == "k_merge_q":
+        b += 16 * n_facts + 16 * n_local_minima  # read every queued fact, settle every slot
     if kernel == "k_local":
         b += 24 * n_local_minima   # write slot + key of every local minimum
     if kernel in ("k_cross", "k_repair_min"):
@@ -367,10 +370,10 @@ def main():
     dt = (t1 - t0) / args.steps
     N = s.N
 
-    n_min = mt.build_stats(s.ws)  # local minima records of the build
+    n_min, n_facts = mt.build_stats(s.ws)  # local minima records and queued cross-tile facts
     dom = max((k for k in kstats if k in ALGO_BYTES_PER_VERTEX), key=lambda k: kstats[k][0])
     avg_s = kstats[dom][0] / kstats[dom][1] / 1e3
-    ab = algo_bytes(dom, N, P, n_min)
+    ab = algo_bytes(dom, N, P, n_min, n_facts)
     achieved = ab / avg_s / 1e9
     traffic = stored_traffic(dom, args.workload)
     roofline = {
@@ -385,7 +388,7 @@ def main():
         "algo_bytes_per_launch": ab,
     }
     per_kernel = {k: {"avg_ms": v[0] / v[1], "launches": v[1]} for k, v in sorted(kstats.items())}
-    path_bytes = sum(algo_bytes(k, N, P, n_min) for k in ALGO_BYTES_PER_VERTEX)
+    path_bytes = sum(algo_bytes(k, N, P, n_min, n_facts) for k in ALGO_BYTES_PER_VERTEX)
 
     out = {
         "metric": "Mvertices/s merge tree+pairs (bit-exact), batched vs plain; %HBM peak; bwd μs",
@@ -401,7 +404,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": args.workload, "shape": list(f.shape), "vertices": N, "connectivity": 6,
-                   "pairs": P, "roots": R, "tile_local_minima": n_min},
+                   "pairs": P, "roots": R, "tile_local_minima": n_min,
+                   "cross_tile_facts": n_facts},
         "roofline": roofline,
         "path_algo_GBps": path_bytes / dt / 1e9,
         "kernels": per_kernel,

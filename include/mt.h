@@ -159,9 +159,10 @@ int mt_sync_status(const void *workspace, void *stream, int64_t *n_pairs, int64_
 /*
  * mt_build_stats -- synchronize `stream` and report, for the last build on
  * `workspace`, the number of tile-local minima the build kept a merge record
- * for (an internal size, reported for measurement).
+ * for and (if n_cross_facts is not NULL) the number of cross-tile merge facts
+ * it queued after de-duplication (internal sizes, reported for measurement).
  */
-int mt_build_stats(const void *workspace, void *stream, int64_t *n_local_minima);
+int mt_build_stats(const void *workspace, void *stream, int64_t *n_local_minima, int64_t *n_cross_facts);
 
 /*
  * mt_pairs_backward -- adjoint of the pair readout.  A pair's birth value is

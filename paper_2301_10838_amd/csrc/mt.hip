@@ -690,7 +690,7 @@ int mt_autotune(const float *fields, const int64_t *dims, int32_t n_fields, uint
     return rc;
 }
 
-int mt_build_stats(const void *workspace, void *stream, int64_t *n_local_minima)
+int mt_build_stats(const void *workspace, void *stream, int64_t *n_local_minima, int64_t *n_cross_facts)
 {
     if (!workspace) return MT_ERR_WORKSPACE;
     if (!n_local_minima) return MT_ERR_INVALID_ARG;
@@ -698,6 +698,11 @@ int mt_build_stats(const void *workspace, void *stream, int64_t *n_local_minima)
     const int rc = read_header(workspace, (hipStream_t)stream, h);
     if (rc != MT_OK) return rc;
     *n_local_minima = h.n_minima;
+    if (n_cross_facts) {
+        int64_t t = 0;
+        for (int x = 0; x < 8; ++x) t += h.n_cross[x];
+        *n_cross_facts = t;
+    }
     return MT_OK;
 }
 

@@ -317,17 +317,25 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
 {
     constexpr int NT = S::NT, VOL = S::VOL, TX = S::TX, TY = S::TY;
     constexpr int HALF = VOL / 2;   // local minima are pairwise non-adjacent: at most half the tile
-    constexpr int H = VOL / 2;      // hash table of basin pairs
-    static_assert(VOL <= 65536, "positions fit 16 bits");
+    // Basin-pair table: one 64-bit word per entry holding the lowest edge of
+    // the pair, (saddle key << 32 | saddle position << 2ZB | lo | hi << ZB),
+    // so claiming an entry and lowering its edge are one word each and the
+    // table is twice as long as a (pair, key) layout in the same space.
+    constexpr int POSB = __builtin_ctz(VOL);     // bits of a tile position
+    constexpr int ZB = (32 - POSB) / 2;          // bits of a minimum number in a tag
+    constexpr uint32_t ZMAX = 1u << ZB;          // tables are used when the tile has at most ZMAX minima
+    constexpr uint64_t TAGM = (1ull << (2 * ZB)) - 1;
+    constexpr int H = VOL;
+    static_assert((VOL & (VOL - 1)) == 0 && POSB + 2 * ZB <= 32, "tag layout");
     __shared__ uint32_t hk[VOL];    // order key of every tile vertex
-    __shared__ int16_t wl[VOL];     // lowest lower neighbour in the tile (self at a local minimum)
+    __shared__ int16_t wl[VOL];     // lowest lower neighbour in the tile (self at a local minimum);
+                                    // later the list of occupied table entries
     __shared__ uint16_t zl[VOL];    // local minimum index of the vertex's local basin
     __shared__ uint32_t TL[HALF];   // triplets of the local minima
     __shared__ uint16_t mh[HALF];   // tile position of local minimum i
-    __shared__ uint32_t hpair[H];   // basin pair (lo | hi << 16) of each table entry
-    __shared__ uint64_t hbest[H];   // lowest key of an edge joining that pair
+    __shared__ uint64_t htab[H];
     __shared__ uint32_t wsum[NT / 64];
-    __shared__ uint32_t sb0;
+    __shared__ uint32_t sb0, nwin;
 
     const int64_t tl = xcd_tile(blockIdx.x, gridDim.x, remap);
     if (tl >= ntiles) return;
@@ -403,10 +411,8 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
     const uint32_t cnt = run;
     if (threadIdx.x == 0) sb0 = atomicAdd(&h->n_minima, cnt);
 
-    for (int i = threadIdx.x; i < H; i += NT) {
-        hpair[i] = 0xffffffffu;
-        hbest[i] = ~0ull;
-    }
+    for (int i = threadIdx.x; i < H; i += NT) htab[i] = ~0ull;
+    if (threadIdx.x == 0) nwin = 0;
 
     // local basins: follow the pointers to the local minimum (keys fall
     // strictly along them, so at most VOL steps)
@@ -431,27 +437,31 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
     // Edges inside the tile whose ends lie in different local basins.  Of all
     // edges joining the same two basins only the lowest (smallest upper end)
     // is merged: the connection it makes at its level implies the connection
-    // every other one would make at a higher level.  A table keyed by the
-    // basin pair keeps that lowest edge; an edge that finds no table room is
-    // merged directly.  Before touching the table, an edge is dropped when the
-    // edge of the same direction one step back in x (or y) joins the same two
-    // basins at a level no higher: "dominated" is a strict order, so the
-    // lowest edge of every pair always reaches the table.
+    // every other one would make at a higher level.  The pair table keeps that
+    // lowest edge; an edge that finds no table room is merged directly, and so
+    // is every edge of a tile with more minima than a tag can number.  Before
+    // touching the table, an edge is dropped when the edge of the same
+    // direction one step back in x (or y) joins the same two basins at a
+    // level no higher: "dominated" is a strict order, so the lowest edge of
+    // every pair always reaches the table.
     uint32_t err = 0;
     const int lane = threadIdx.x & 63;
-    auto insert = [&](uint32_t key, uint64_t ks, uint32_t za, uint32_t zb) {
-        uint32_t si = (key * 0x9E3779B1u) >> (32 - __builtin_ctz(H));
+    const bool tabled = (uint32_t)HALF <= ZMAX || cnt <= ZMAX;
+    auto insert = [&](uint64_t val, uint32_t za, uint32_t zb) {
+        const uint32_t tag = (uint32_t)(val & TAGM);
+        uint32_t si = (tag * 0x9E3779B1u) >> (32 - POSB);
         for (int probe = 0; probe < 32; ++probe) {
-            uint32_t prev = 0xffffffffu;
-            __hip_atomic_compare_exchange_strong(hpair + si, &prev, key, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+            uint64_t prev = ~0ull;
+            __hip_atomic_compare_exchange_strong(htab + si, &prev, val, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                                  __HIP_MEMORY_SCOPE_WORKGROUP);
-            if (prev == 0xffffffffu || prev == key) {
-                atomicMin((unsigned long long *)(hbest + si), (unsigned long long)ks);
+            if (prev == ~0ull) return;
+            if ((prev & TAGM) == tag) {
+                if (val < prev) atomicMin((unsigned long long *)(htab + si), (unsigned long long)val);
                 return;
             }
             si = (si + 1) & (H - 1);
         }
-        lds_merge<HALF>(TL, hk, mh, za, (uint32_t)lo32(ks), zb, cap, err);
+        lds_merge<HALF>(TL, hk, mh, za, (uint32_t)(val >> (2 * ZB)) & (VOL - 1), zb, cap, err);
     };
     for (int p = threadIdx.x; p < VOL; p += NT) {  // same trip count in every lane (VOL % NT == 0)
         const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
@@ -462,33 +472,51 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
         for (int dir = 0; dir < 3; ++dir) {
             const int q = p + (dir == 0 ? 1 : dir == 1 ? TX : TX * TY);
             const bool edge = ok && (dir == 0 ? lx + 1 < c.ex : dir == 1 ? ly + 1 < c.ey : lz + 1 < c.ez);
-            uint32_t key = 0xffffffffu, zb = 0;
-            uint64_t ks = ~0ull;
+            uint64_t val = ~0ull;  // never a real entry: a tag has lo < hi
+            uint32_t zb = 0, sp = 0;
+            bool cand = false;
             if (edge) {
                 zb = zl[q];
-                if (zb != za) {
+                cand = zb != za;
+                if (cand) {
                     const uint64_t kb = tkey(hk, q);
-                    ks = kb < ka ? ka : kb;
-                    key = min(za, zb) | (max(za, zb) << 16);
+                    sp = kb < ka ? (uint32_t)p : (uint32_t)q;  // upper end
+                    val = ((uint64_t)hk[sp] << 32) | ((uint64_t)sp << (2 * ZB)) | min(za, zb) |
+                          ((uint64_t)max(za, zb) << ZB);  // meaningful only when tabled
                 }
             }
-            const uint32_t key1 = __shfl_up(key, 1);
-            const uint64_t ks1 = ((uint64_t)__shfl_up((uint32_t)(ks >> 32), 1) << 32) | __shfl_up((uint32_t)ks, 1);
-            bool dom = lane >= 1 && lx > 0 && key1 == key && ks1 <= ks;
-            if (TX < 64) {
-                const uint32_t key2 = __shfl_up(key, TX);
-                const uint64_t ks2 =
-                    ((uint64_t)__shfl_up((uint32_t)(ks >> 32), TX) << 32) | __shfl_up((uint32_t)ks, TX);
-                dom = dom || (lane >= TX && ly > 0 && key2 == key && ks2 <= ks);
+            if (!tabled) {
+                if (cand) lds_merge<HALF>(TL, hk, mh, za, sp, zb, cap, err);
+                continue;
             }
-            if (key != 0xffffffffu && !dom) insert(key, ks, za, zb);
+            auto same_lower = [&](uint64_t o) { return ((o ^ val) & TAGM) == 0 && o <= val; };
+            const uint64_t v1 = ((uint64_t)__shfl_up((uint32_t)(val >> 32), 1) << 32) | __shfl_up((uint32_t)val, 1);
+            bool dom = lane >= 1 && lx > 0 && same_lower(v1);
+            if (TX < 64) {
+                const uint64_t v2 =
+                    ((uint64_t)__shfl_up((uint32_t)(val >> 32), TX) << 32) | __shfl_up((uint32_t)val, TX);
+                dom = dom || (lane >= TX && ly > 0 && same_lower(v2));
+            }
+            if (cand && !dom) insert(val, za, zb);
         }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < H; i += NT) {
-        const uint32_t key = hpair[i];
-        if (key == 0xffffffffu) continue;
-        lds_merge<HALF>(TL, hk, mh, key & 0xffffu, (uint32_t)lo32(hbest[i]), key >> 16, cap, err);
+    // occupied entries, compacted so that every lane of a wave has a merge
+    for (int i0 = 0; i0 < H; i0 += NT) {
+        const int i = i0 + threadIdx.x;
+        const bool occ = i < H && htab[i] != ~0ull;
+        const uint64_t m = __ballot(occ);
+        uint32_t base = 0;
+        if (lane == 0 && m) base = atomicAdd(&nwin, (uint32_t)__popcll(m));
+        base = __shfl(base, 0);
+        if (occ) wl[base + (uint32_t)__popcll(m & lanemask_lt())] = (int16_t)i;
+    }
+    __syncthreads();
+    const uint32_t nw = nwin;
+    for (uint32_t i = threadIdx.x; i < nw; i += NT) {
+        const uint64_t e = htab[(uint16_t)wl[i]];
+        const uint32_t tag = (uint32_t)(e & TAGM);
+        lds_merge<HALF>(TL, hk, mh, tag & (ZMAX - 1), (uint32_t)(e >> (2 * ZB)) & (VOL - 1), tag >> ZB, cap, err);
     }
     __syncthreads();
 

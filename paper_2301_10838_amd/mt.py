@@ -67,7 +67,7 @@ def load_library():
     lib.mt_batch_build.restype = ctypes.c_int
     lib.mt_sync_status.argtypes = [P, P, P, P]
     lib.mt_sync_status.restype = ctypes.c_int
-    lib.mt_build_stats.argtypes = [P, P, P]
+    lib.mt_build_stats.argtypes = [P, P, P, P]
     lib.mt_build_stats.restype = ctypes.c_int
     lib.mt_pairs_backward.argtypes = [P, I32, P, I64, P, P, P, P, P, ctypes.c_int, P]
     lib.mt_pairs_backward.restype = ctypes.c_int
@@ -324,12 +324,13 @@ def profile_end():
     return out
 
 
-def build_stats(workspace: torch.Tensor) -> int:
-    """Tile-local minima of the last build on this workspace (synchronizes)."""
-    n = ctypes.c_int64(0)
-    _check(load_library().mt_build_stats(workspace.data_ptr(), _stream_ptr(workspace.device), ctypes.byref(n)),
-           "mt_build_stats")
-    return n.value
+def build_stats(workspace: torch.Tensor):
+    """(tile-local minima, cross-tile facts) of the last build on this
+    workspace (synchronizes)."""
+    n, q = ctypes.c_int64(0), ctypes.c_int64(0)
+    _check(load_library().mt_build_stats(workspace.data_ptr(), _stream_ptr(workspace.device), ctypes.byref(n),
+                                         ctypes.byref(q)), "mt_build_stats")
+    return n.value, q.value
 
 
 def tile_shapes():

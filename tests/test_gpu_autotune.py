@@ -56,3 +56,26 @@ def test_tune_driver_cache(tmp_path, monkeypatch):
     finally:
         for c, sid in before.items():
             mt.set_tile_shape(c, sid)
+
+
+def test_every_shape_checkerboard():
+    """Tiles with as many local minima as a tile can hold (every other vertex)
+    take the direct-merge path of the tile pass on every compiled shape."""
+    import paper_2301_10838_amd.mt as mt
+
+    dev = device()
+    before = {c: mt.get_tile_shape(c) for c in range(3)}
+    try:
+        for s in mt.tile_shapes():
+            c = s["dims_class"]
+            ext = [2 * s["tx"] + 3, 2 * s["ty"] + 1, 2 * s["tz"] + 1][: 3 - c]
+            idx = np.indices(ext[::-1])
+            f = (idx.sum(0) % 2).astype(np.float32)
+            mt.set_tile_shape(c, s["id"])
+            print("case checkerboard", s, f.shape, flush=True)
+            T, prs = gpu_tree(f, dev)
+            assert np.array_equal(T, oracle.merge_tree(f)), s
+            assert prs[0].size == (f.size + 1) // 2 - 1, s
+    finally:
+        for c, sid in before.items():
+            mt.set_tile_shape(c, sid)
