@@ -122,6 +122,15 @@ class Single:
             raise self.mt.MTError(rc, "mt_persistence_pairs")
         return self.np.value, self.nr.value
 
+    def build_stats(self):
+        """Internal sizes of a build alone (the pairs call reuses the header)."""
+        nx, ny, nz = self.dims
+        rc = self.lib.mt_build(self.ft.data_ptr(), nx, ny, nz, self.T.data_ptr(), self.ws.data_ptr(),
+                               self.ws.numel(), self.stream)
+        if rc != 0:
+            raise self.mt.MTError(rc, "mt_build")
+        return self.mt.build_stats(self.ws)
+
 
 def cpu_baseline(f: np.ndarray, dev, mt, lib):
     """Oracle (serial, one core) on a bounded slab of the workload, and the GPU
@@ -370,7 +379,7 @@ def main():
     dt = (t1 - t0) / args.steps
     N = s.N
 
-    n_min, n_facts = mt.build_stats(s.ws)  # local minima records and queued cross-tile facts
+    n_min, n_facts = s.build_stats()  # local minima records and queued cross-tile facts (untimed)
     dom = max((k for k in kstats if k in ALGO_BYTES_PER_VERTEX), key=lambda k: kstats[k][0])
     avg_s = kstats[dom][0] / kstats[dom][1] / 1e3
     ab = algo_bytes(dom, N, P, n_min, n_facts)

@@ -262,47 +262,66 @@ __global__ void k_setup(SetupArgs a, FieldDesc *D, int32_t *tfield, int64_t *tst
 // ---------------------------------------------------------------------------
 // 1. merge tree of each tile's subgraph, in LDS
 
-// LDS triplet of local minimum i: low 16 bits = saddle (position in the tile),
-// high 16 bits = target (local minimum index).
-__device__ __forceinline__ uint64_t tkey(const uint32_t *hk, uint32_t p) { return ((uint64_t)hk[p] << 32) | p; }
+// Tile order key of tile position p: (order key of the value << PB) | p, PB =
+// log2 of the tile volume.  It orders tile vertices exactly as the global key
+// does (positions grow with the id inside a tile).
+template <int PB>
+__device__ __forceinline__ uint64_t lkey(const uint32_t *hk, uint32_t p)
+{
+    return ((uint64_t)hk[p] << PB) | p;
+}
 
-__device__ __forceinline__ uint32_t lds_ld(uint32_t *p)
+// LDS triplet of local minimum i, one 64-bit word: (tile key of the saddle <<
+// TB) | target (local minimum index).  A root is (own key, own index).  A
+// descent step is one load and one compare, and the word is replaced by one
+// 64-bit compare-and-swap.
+template <int VOL>
+struct LTrip {
+    static constexpr int PB = __builtin_ctz(VOL);
+    static constexpr int TB = 32 - PB;                 // target bits
+    static constexpr uint64_t TM = (1ull << TB) - 1;
+    static_assert(PB - 1 <= TB, "every local minimum index fits the target bits");
+    __device__ static uint64_t make(uint64_t key, uint32_t t) { return (key << TB) | t; }
+    __device__ static uint32_t tgt(uint64_t w) { return (uint32_t)(w & TM); }
+    __device__ static uint64_t key(uint64_t w) { return w >> TB; }
+};
+
+__device__ __forceinline__ uint64_t lds_ld64(uint64_t *p)
 {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// Merge (Alg. 3) of "local minima u and v are connected at level s" (s a tile
-// position).  Descents stop at roots; after a swap that replaced a root
+// Merge (Alg. 3) of "local minima u and v are connected at the level whose
+// tile key is ks".  Descents stop at roots; after a swap that replaced a root
 // nothing was displaced; otherwise the displaced triplet is merged again from
 // the lower minimum; a lost swap restarts with the value it saw.
 template <int VOL>
-__device__ void lds_merge(uint32_t *TL, const uint32_t *hk, const uint16_t *mh, uint32_t u, uint32_t s,
-                          uint32_t v, uint32_t cap, uint32_t &err)
+__device__ void lds_merge(uint64_t *TL, const uint32_t *hk, const uint16_t *mh, uint32_t u, uint64_t ks,
+                          uint32_t v, uint32_t cnt, uint32_t cap, uint32_t &err)
 {
-    uint64_t ks = tkey(hk, s);
-    uint32_t tu = lds_ld(TL + u), tv = lds_ld(TL + v);
+    using L = LTrip<VOL>;
+    uint64_t tu = lds_ld64(TL + u), tv = lds_ld64(TL + v);
     for (uint32_t step = 0; step < cap; ++step) {
-        const uint32_t u1 = tu >> 16, su = tu & 0xffffu, v1 = tv >> 16, sv = tv & 0xffffu;
-        if (u1 >= (uint32_t)VOL || v1 >= (uint32_t)VOL) { err |= ST_CORRUPT; return; }
-        if (u1 != u && tkey(hk, su) < ks) { u = u1; tu = lds_ld(TL + u); continue; }
-        if (v1 != v && tkey(hk, sv) < ks) { v = v1; tv = lds_ld(TL + v); continue; }
+        const uint32_t u1 = L::tgt(tu), v1 = L::tgt(tv);
+        if (u1 >= cnt || v1 >= cnt) { err |= ST_CORRUPT; return; }
+        if (u1 != u && L::key(tu) < ks) { u = u1; tu = lds_ld64(TL + u); continue; }
+        if (v1 != v && L::key(tv) < ks) { v = v1; tv = lds_ld64(TL + v); continue; }
         if (u == v) return;
-        if (tkey(hk, mh[v]) < tkey(hk, mh[u])) {
+        if (lkey<L::PB>(hk, mh[v]) < lkey<L::PB>(hk, mh[u])) {
             const uint32_t w = u; u = v; v = w;
-            const uint32_t tw = tu; tu = tv; tv = tw;
+            const uint64_t tw = tu; tu = tv; tv = tw;
         }
-        uint32_t seen = tv;
-        if (__hip_atomic_compare_exchange_strong(TL + v, &seen, s | (u << 16), __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_WORKGROUP)) {
-            if ((tv >> 16) == v) return;
-            s = tv & 0xffffu;
-            ks = tkey(hk, s);
-            v = tv >> 16;
-            tv = lds_ld(TL + v);
+        uint64_t seen = tv;
+        if (__hip_atomic_compare_exchange_strong(TL + v, &seen, L::make(ks, u), __ATOMIC_RELAXED,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) {
+            if (L::tgt(tv) == v) return;
+            ks = L::key(tv);
+            v = L::tgt(tv);
+            tv = lds_ld64(TL + v);
         } else {
             tv = seen;
         }
-        tu = lds_ld(TL + u);
+        tu = lds_ld64(TL + u);
     }
     err |= ST_LIVELOCK;
 }
@@ -317,23 +336,26 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
 {
     constexpr int NT = S::NT, VOL = S::VOL, TX = S::TX, TY = S::TY;
     constexpr int HALF = VOL / 2;   // local minima are pairwise non-adjacent: at most half the tile
+    using L = LTrip<VOL>;
+    constexpr int PB = L::PB;
     // Basin-pair table: one 64-bit word per entry holding the lowest edge of
-    // the pair, (saddle key << 32 | saddle position << 2ZB | lo | hi << ZB),
-    // so claiming an entry and lowering its edge are one word each and the
-    // table is twice as long as a (pair, key) layout in the same space.
-    constexpr int POSB = __builtin_ctz(VOL);     // bits of a tile position
-    constexpr int ZB = (32 - POSB) / 2;          // bits of a minimum number in a tag
-    constexpr uint32_t ZMAX = 1u << ZB;          // tables are used when the tile has at most ZMAX minima
+    // the pair, (tile key of its upper end << 2ZB | lo | hi << ZB), so
+    // claiming an entry and lowering its edge are one word each.
+    constexpr int ZB = (32 - PB) / 2;            // bits of a minimum number in a tag
+    constexpr uint32_t ZMAX = 1u << ZB;          // the table is used when the tile has at most ZMAX minima
     constexpr uint64_t TAGM = (1ull << (2 * ZB)) - 1;
     constexpr int H = VOL;
-    static_assert((VOL & (VOL - 1)) == 0 && POSB + 2 * ZB <= 32, "tag layout");
+    static_assert((VOL & (VOL - 1)) == 0 && PB + 2 * ZB <= 32, "tag layout");
     __shared__ uint32_t hk[VOL];    // order key of every tile vertex
-    __shared__ int16_t wl[VOL];     // lowest lower neighbour in the tile (self at a local minimum);
-                                    // later the list of occupied table entries
     __shared__ uint16_t zl[VOL];    // local minimum index of the vertex's local basin
-    __shared__ uint32_t TL[HALF];   // triplets of the local minima
+    __shared__ uint64_t TL[HALF];   // triplets of the local minima
     __shared__ uint16_t mh[HALF];   // tile position of local minimum i
+    // The lowest-neighbour pointers are dead once the basins are known; the
+    // table takes their place.
     __shared__ uint64_t htab[H];
+    typedef int16_t __attribute__((may_alias)) i16a;
+    i16a *const wl = (i16a *)htab;  // lowest lower neighbour in the tile (self at a local minimum)
+    static_assert(sizeof(int16_t) * VOL <= sizeof(uint64_t) * H, "aliasing");
     __shared__ uint32_t wsum[NT / 64];
     __shared__ uint32_t sb0, nwin;
 
@@ -366,11 +388,11 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
     for (int p = threadIdx.x; p < VOL; p += NT) {
         const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
         if (!valid(lx, ly, lz)) continue;
-        uint64_t best = tkey(hk, p);
+        uint64_t best = lkey<PB>(hk, p);
         int bp = p;
 #define MT_CAND(cond, q)                                                                    \
         if (cond) {                                                                         \
-            const uint64_t k = tkey(hk, (q));                                               \
+            const uint64_t k = lkey<PB>(hk, (q));                                           \
             if (k < best) { best = k; bp = (q); }                                          \
         }
         MT_CAND(lx > 0, p - 1)
@@ -403,16 +425,16 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
             const uint32_t r = run + wb + (uint32_t)__popcll(m & lanemask_lt());
             zl[p] = (uint16_t)r;
             mh[r] = (uint16_t)p;
-            TL[r] = (uint32_t)p | (r << 16);
+            TL[r] = L::make(lkey<PB>(hk, p), r);
         }
         run += tot;
         __syncthreads();
     }
     const uint32_t cnt = run;
-    if (threadIdx.x == 0) sb0 = atomicAdd(&h->n_minima, cnt);
-
-    for (int i = threadIdx.x; i < H; i += NT) htab[i] = ~0ull;
-    if (threadIdx.x == 0) nwin = 0;
+    if (threadIdx.x == 0) {
+        sb0 = atomicAdd(&h->n_minima, cnt);
+        nwin = 0;
+    }
 
     // local basins: follow the pointers to the local minimum (keys fall
     // strictly along them, so at most VOL steps)
@@ -433,6 +455,8 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
         if (threadIdx.x == 0) atomicOr(&h->status, ST_CORRUPT);
         return;
     }
+    for (int i = threadIdx.x; i < H; i += NT) htab[i] = ~0ull;
+    __syncthreads();
 
     // Edges inside the tile whose ends lie in different local basins.  Of all
     // edges joining the same two basins only the lowest (smallest upper end)
@@ -449,7 +473,7 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
     const bool tabled = (uint32_t)HALF <= ZMAX || cnt <= ZMAX;
     auto insert = [&](uint64_t val, uint32_t za, uint32_t zb) {
         const uint32_t tag = (uint32_t)(val & TAGM);
-        uint32_t si = (tag * 0x9E3779B1u) >> (32 - POSB);
+        uint32_t si = (tag * 0x9E3779B1u) >> (32 - PB);
         for (int probe = 0; probe < 32; ++probe) {
             uint64_t prev = ~0ull;
             __hip_atomic_compare_exchange_strong(htab + si, &prev, val, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
@@ -461,32 +485,31 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
             }
             si = (si + 1) & (H - 1);
         }
-        lds_merge<HALF>(TL, hk, mh, za, (uint32_t)(val >> (2 * ZB)) & (VOL - 1), zb, cap, err);
+        lds_merge<VOL>(TL, hk, mh, za, val >> (2 * ZB), zb, cnt, cap, err);
     };
     for (int p = threadIdx.x; p < VOL; p += NT) {  // same trip count in every lane (VOL % NT == 0)
         const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
         const bool ok = valid(lx, ly, lz);
         const uint32_t za = ok ? zl[p] : 0u;
-        const uint64_t ka = ok ? tkey(hk, p) : 0ull;
+        const uint64_t ka = ok ? lkey<PB>(hk, p) : 0ull;
 #pragma unroll
         for (int dir = 0; dir < 3; ++dir) {
             const int q = p + (dir == 0 ? 1 : dir == 1 ? TX : TX * TY);
             const bool edge = ok && (dir == 0 ? lx + 1 < c.ex : dir == 1 ? ly + 1 < c.ey : lz + 1 < c.ez);
-            uint64_t val = ~0ull;  // never a real entry: a tag has lo < hi
-            uint32_t zb = 0, sp = 0;
+            uint64_t ks = 0, val = ~0ull;  // ~0 is never a real entry: a tag has lo < hi
+            uint32_t zb = 0;
             bool cand = false;
             if (edge) {
                 zb = zl[q];
                 cand = zb != za;
                 if (cand) {
-                    const uint64_t kb = tkey(hk, q);
-                    sp = kb < ka ? (uint32_t)p : (uint32_t)q;  // upper end
-                    val = ((uint64_t)hk[sp] << 32) | ((uint64_t)sp << (2 * ZB)) | min(za, zb) |
-                          ((uint64_t)max(za, zb) << ZB);  // meaningful only when tabled
+                    const uint64_t kb = lkey<PB>(hk, q);
+                    ks = kb < ka ? ka : kb;  // the upper end is the saddle
+                    val = (ks << (2 * ZB)) | min(za, zb) | ((uint64_t)max(za, zb) << ZB);  // if tabled
                 }
             }
             if (!tabled) {
-                if (cand) lds_merge<HALF>(TL, hk, mh, za, sp, zb, cap, err);
+                if (cand) lds_merge<VOL>(TL, hk, mh, za, ks, zb, cnt, cap, err);
                 continue;
             }
             auto same_lower = [&](uint64_t o) { return ((o ^ val) & TAGM) == 0 && o <= val; };
@@ -501,50 +524,63 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
         }
     }
     __syncthreads();
-    // occupied entries, compacted so that every lane of a wave has a merge
-    for (int i0 = 0; i0 < H; i0 += NT) {
-        const int i = i0 + threadIdx.x;
-        const bool occ = i < H && htab[i] != ~0ull;
-        const uint64_t m = __ballot(occ);
-        uint32_t base = 0;
-        if (lane == 0 && m) base = atomicAdd(&nwin, (uint32_t)__popcll(m));
-        base = __shfl(base, 0);
-        if (occ) wl[base + (uint32_t)__popcll(m & lanemask_lt())] = (int16_t)i;
+    // Occupied entries, compacted to the front of the table so that every
+    // lane of a wave has a merge: each lane holds its entries while the
+    // table is rewritten.
+    {
+        constexpr int PER = (H + NT - 1) / NT;
+        uint64_t e[PER];
+        uint32_t pos[PER];
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int i = k * NT + threadIdx.x;
+            e[k] = i < H ? htab[i] : ~0ull;
+            const bool occ = e[k] != ~0ull;
+            const uint64_t m = __ballot(occ);
+            uint32_t base = 0;
+            if (lane == 0 && m) base = atomicAdd(&nwin, (uint32_t)__popcll(m));
+            base = __shfl(base, 0);
+            pos[k] = base + (uint32_t)__popcll(m & lanemask_lt());
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < PER; ++k)
+            if (e[k] != ~0ull) htab[pos[k]] = e[k];
     }
     __syncthreads();
     const uint32_t nw = nwin;
     for (uint32_t i = threadIdx.x; i < nw; i += NT) {
-        const uint64_t e = htab[(uint16_t)wl[i]];
+        const uint64_t e = htab[i];
         const uint32_t tag = (uint32_t)(e & TAGM);
-        lds_merge<HALF>(TL, hk, mh, tag & (ZMAX - 1), (uint32_t)(e >> (2 * ZB)) & (VOL - 1), tag >> ZB, cap, err);
+        lds_merge<VOL>(TL, hk, mh, tag & (ZMAX - 1), e >> (2 * ZB), tag >> ZB, cnt, cap, err);
     }
     __syncthreads();
 
     // Repair (Alg. 5) of the local minima: target -> deepest local minimum
     // reached through links whose saddle is at or below the minimum's own.
     for (uint32_t i = threadIdx.x; i < cnt; i += NT) {
-        const uint32_t t = lds_ld(TL + i);
-        const uint32_t s = t & 0xffffu;
-        uint32_t x = t >> 16;
+        const uint64_t t = lds_ld64(TL + i);
+        uint32_t x = L::tgt(t);
         if (x == i) continue;
-        const uint64_t ks = tkey(hk, s);
+        const uint64_t ks = L::key(t);
         for (uint32_t step = 0; step < cap; ++step) {
-            const uint32_t tx = lds_ld(TL + x);
-            const uint32_t v = tx >> 16;
+            const uint64_t tx = lds_ld64(TL + x);
+            const uint32_t v = L::tgt(tx);
             if (v >= cnt) { err |= ST_CORRUPT; break; }
-            if (v == x || tkey(hk, tx & 0xffffu) > ks) break;
+            if (v == x || L::key(tx) > ks) break;
             x = v;
         }
-        if (x != (t >> 16)) __hip_atomic_store(TL + i, s | (x << 16), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (x != L::tgt(t))
+            __hip_atomic_store(TL + i, L::make(ks, x), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
     __syncthreads();
 
     for (uint32_t i = threadIdx.x; i < cnt; i += NT) {
-        const uint32_t t = TL[i];
-        const uint32_t sp = t & 0xffffu, mp = mh[i];
+        const uint64_t t = TL[i];
+        const uint32_t sp = (uint32_t)L::key(t) & (VOL - 1), mp = mh[i];
         const uint32_t sg = gid((int)sp);
-        slot[b0 + i].w = pack(sg, b0 + (t >> 16));
-        slot[b0 + i].k = ((uint64_t)hk[sp] << 32) | sg;
+        slot[b0 + i].w = pack(sg, b0 + L::tgt(t));
+        slot[b0 + i].k = ((uint64_t)(uint32_t)(L::key(t) >> PB) << 32) | sg;
         mkey[b0 + i] = ((uint64_t)hk[mp] << 32) | gid((int)mp);
     }
     // Every vertex is labelled with the representative of its local basin
@@ -555,12 +591,12 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
         const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
         if (!valid(lx, ly, lz)) continue;
         uint32_t x = zl[p];
-        const uint64_t level = tkey(hk, p);
+        const uint64_t level = lkey<PB>(hk, p);
         for (uint32_t step = 0; step < cap; ++step) {
-            const uint32_t t = TL[x];
-            const uint32_t v = t >> 16;
+            const uint64_t t = TL[x];
+            const uint32_t v = L::tgt(t);
             if (v >= cnt) { err |= ST_CORRUPT; break; }
-            if (v == x || tkey(hk, t & 0xffffu) > level) break;
+            if (v == x || L::key(t) > level) break;
             x = v;
         }
         lbl[gid(p)] = b0 + x;
