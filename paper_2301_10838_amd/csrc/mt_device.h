@@ -363,37 +363,52 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
     if (tl >= ntiles) return;
     const TileCtx c = tile_ctx<S>(D, tfield, tstart, nfc, tile0 + tl);
     const uint32_t off = (uint32_t)c.d.offset;
-    const float *__restrict__ fb = f + off;
     auto valid = [&](int lx, int ly, int lz) { return lx < c.ex && ly < c.ey && lz < c.ez; };
+    // Ids in 32 bits: every id of the batch is below 2^31.
+    const uint32_t nx = (uint32_t)c.d.nx, sxy = (uint32_t)c.sxy;
+    const uint32_t base = off + (uint32_t)c.x0 + nx * (uint32_t)c.y0 + sxy * (uint32_t)c.z0;
+    auto lid = [&](int lx, int ly, int lz) { return (uint32_t)lx + nx * (uint32_t)ly + sxy * (uint32_t)lz; };
     auto gid = [&](int p) {
         const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
-        return off + (uint32_t)((c.x0 + lx) + (int64_t)c.d.nx * (c.y0 + ly) + c.sxy * (c.z0 + lz));
+        return base + lid(lx, ly, lz);
     };
+    constexpr int PER = VOL / NT;  // vertices per lane
 
-    bool nan = false;
-    for (int p = threadIdx.x; p < VOL; p += NT) {
-        const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
-        uint32_t k = 0xffffffffu;
-        if (valid(lx, ly, lz)) {
-            const float v = fb[(c.x0 + lx) + (int64_t)c.d.nx * (c.y0 + ly) + c.sxy * (c.z0 + lz)];
-            nan |= (v != v);
-            k = okey(v);
+    {
+        // all of a lane's loads in flight together; positions outside the
+        // field read a clamped in-field address and are then discarded
+        float fv[PER];
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int p = k * NT + threadIdx.x;
+            const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
+            fv[k] = f[base + lid(min(lx, c.ex - 1), min(ly, c.ey - 1), min(lz, c.ez - 1))];
         }
-        hk[p] = k;
+        bool nan = false;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int p = k * NT + threadIdx.x;
+            const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
+            const bool ok = valid(lx, ly, lz);
+            nan |= ok && (fv[k] != fv[k]);
+            hk[p] = ok ? okey(fv[k]) : 0xffffffffu;
+        }
+        if (__ballot(nan) != 0ull && (threadIdx.x & 63) == 0) atomicOr(&h->status, ST_NAN);
     }
-    if (__ballot(nan) != 0ull && (threadIdx.x & 63) == 0) atomicOr(&h->status, ST_NAN);
     __syncthreads();
 
     // lowest lower neighbour inside the tile
-    for (int p = threadIdx.x; p < VOL; p += NT) {
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int p = k * NT + threadIdx.x;
         const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
         if (!valid(lx, ly, lz)) continue;
         uint64_t best = lkey<PB>(hk, p);
         int bp = p;
 #define MT_CAND(cond, q)                                                                    \
         if (cond) {                                                                         \
-            const uint64_t k = lkey<PB>(hk, (q));                                           \
-            if (k < best) { best = k; bp = (q); }                                          \
+            const uint64_t kq = lkey<PB>(hk, (q));                                          \
+            if (kq < best) { best = kq; bp = (q); }                                        \
         }
         MT_CAND(lx > 0, p - 1)
         MT_CAND(lx + 1 < c.ex, p + 1)
