@@ -300,6 +300,7 @@ __device__ void lds_merge(uint64_t *TL, const uint32_t *hk, const uint16_t *mh, 
                           uint32_t v, uint32_t cnt, uint32_t cap, uint32_t &err)
 {
     using L = LTrip<VOL>;
+    if (u >= cnt || v >= cnt) { err |= ST_CORRUPT; return; }
     uint64_t tu = lds_ld64(TL + u), tv = lds_ld64(TL + v);
     for (uint32_t step = 0; step < cap; ++step) {
         const uint32_t u1 = L::tgt(tu), v1 = L::tgt(tv);
@@ -356,8 +357,8 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
     typedef int16_t __attribute__((may_alias)) i16a;
     i16a *const wl = (i16a *)htab;  // lowest lower neighbour in the tile (self at a local minimum)
     static_assert(sizeof(int16_t) * VOL <= sizeof(uint64_t) * H, "aliasing");
-    __shared__ uint32_t wsum[NT / 64];
-    __shared__ uint32_t sb0, nwin;
+    __shared__ uint32_t wsum[VOL / 64];
+    __shared__ uint32_t sb0, nwin, scnt;
 
     const int64_t tl = xcd_tile(blockIdx.x, gridDim.x, remap);
     if (tl >= ntiles) return;
@@ -421,35 +422,51 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
     }
     __syncthreads();
 
-    // number the local minima in tile order; root triplets
-    uint32_t run = 0;
-    const int wave = threadIdx.x >> 6;
-    for (int r0 = 0; r0 < VOL; r0 += NT) {
-        const int p = r0 + threadIdx.x;
-        const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
-        const bool is_min = valid(lx, ly, lz) && wl[p] == p;
-        const uint64_t m = __ballot(is_min);
-        if ((threadIdx.x & 63) == 0) wsum[wave] = (uint32_t)__popcll(m);
-        __syncthreads();
-        uint32_t wb = 0, tot = 0;
-        for (int w = 0; w < NT / 64; ++w) {
-            wb += (w < wave) ? wsum[w] : 0u;
-            tot += wsum[w];
+    // Number the local minima in tile order (position k * NT + thread):
+    // per-wave ballots, one scan of the VOL / 64 wave counts by wave 0.
+    constexpr int NW = NT / 64;
+    static_assert(VOL / 64 <= 64, "one wave scans the counts");
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    {
+        bool is_min[PER];
+        uint64_t mb[PER];
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int p = k * NT + threadIdx.x;
+            const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
+            is_min[k] = valid(lx, ly, lz) && wl[p] == p;
+            mb[k] = __ballot(is_min[k]);
+            if (lane == 0) wsum[k * NW + wave] = (uint32_t)__popcll(mb[k]);
         }
-        if (is_min) {
-            const uint32_t r = run + wb + (uint32_t)__popcll(m & lanemask_lt());
+        __syncthreads();
+        if (wave == 0) {
+            const uint32_t own = lane < VOL / 64 ? wsum[lane] : 0u;
+            uint32_t inc = own;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t t = __shfl_up(inc, o);
+                if (lane >= o) inc += t;
+            }
+            if (lane < VOL / 64) wsum[lane] = inc - own;
+            if (lane == 63) {
+                scnt = inc;
+                sb0 = atomicAdd(&h->n_minima, inc);
+                nwin = 0;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            if (!is_min[k]) continue;
+            const int p = k * NT + threadIdx.x;
+            const uint32_t r = wsum[k * NW + wave] + (uint32_t)__popcll(mb[k] & lanemask_lt());
             zl[p] = (uint16_t)r;
             mh[r] = (uint16_t)p;
             TL[r] = L::make(lkey<PB>(hk, p), r);
         }
-        run += tot;
-        __syncthreads();
     }
-    const uint32_t cnt = run;
-    if (threadIdx.x == 0) {
-        sb0 = atomicAdd(&h->n_minima, cnt);
-        nwin = 0;
-    }
+    __syncthreads();  // the basin pass reads the minima's numbers
+    const uint32_t cnt = scnt;
 
     // local basins: follow the pointers to the local minimum (keys fall
     // strictly along them, so at most VOL steps)
@@ -478,13 +495,8 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
     // is merged: the connection it makes at its level implies the connection
     // every other one would make at a higher level.  The pair table keeps that
     // lowest edge; an edge that finds no table room is merged directly, and so
-    // is every edge of a tile with more minima than a tag can number.  Before
-    // touching the table, an edge is dropped when the edge of the same
-    // direction one step back in x (or y) joins the same two basins at a
-    // level no higher: "dominated" is a strict order, so the lowest edge of
-    // every pair always reaches the table.
+    // is every edge of a tile with more minima than a tag can number.
     uint32_t err = 0;
-    const int lane = threadIdx.x & 63;
     const bool tabled = (uint32_t)HALF <= ZMAX || cnt <= ZMAX;
     auto insert = [&](uint64_t val, uint32_t za, uint32_t zb) {
         const uint32_t tag = (uint32_t)(val & TAGM);
@@ -502,7 +514,7 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
         }
         lds_merge<VOL>(TL, hk, mh, za, val >> (2 * ZB), zb, cnt, cap, err);
     };
-    for (int p = threadIdx.x; p < VOL; p += NT) {  // same trip count in every lane (VOL % NT == 0)
+    for (int p = threadIdx.x; p < VOL; p += NT) {
         const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
         const bool ok = valid(lx, ly, lz);
         const uint32_t za = ok ? zl[p] : 0u;
@@ -511,31 +523,15 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
         for (int dir = 0; dir < 3; ++dir) {
             const int q = p + (dir == 0 ? 1 : dir == 1 ? TX : TX * TY);
             const bool edge = ok && (dir == 0 ? lx + 1 < c.ex : dir == 1 ? ly + 1 < c.ey : lz + 1 < c.ez);
-            uint64_t ks = 0, val = ~0ull;  // ~0 is never a real entry: a tag has lo < hi
-            uint32_t zb = 0;
-            bool cand = false;
-            if (edge) {
-                zb = zl[q];
-                cand = zb != za;
-                if (cand) {
-                    const uint64_t kb = lkey<PB>(hk, q);
-                    ks = kb < ka ? ka : kb;  // the upper end is the saddle
-                    val = (ks << (2 * ZB)) | min(za, zb) | ((uint64_t)max(za, zb) << ZB);  // if tabled
-                }
-            }
-            if (!tabled) {
-                if (cand) lds_merge<VOL>(TL, hk, mh, za, ks, zb, cnt, cap, err);
-                continue;
-            }
-            auto same_lower = [&](uint64_t o) { return ((o ^ val) & TAGM) == 0 && o <= val; };
-            const uint64_t v1 = ((uint64_t)__shfl_up((uint32_t)(val >> 32), 1) << 32) | __shfl_up((uint32_t)val, 1);
-            bool dom = lane >= 1 && lx > 0 && same_lower(v1);
-            if (TX < 64) {
-                const uint64_t v2 =
-                    ((uint64_t)__shfl_up((uint32_t)(val >> 32), TX) << 32) | __shfl_up((uint32_t)val, TX);
-                dom = dom || (lane >= TX && ly > 0 && same_lower(v2));
-            }
-            if (cand && !dom) insert(val, za, zb);
+            if (!edge) continue;
+            const uint32_t zb = zl[q];
+            if (zb == za) continue;
+            const uint64_t kb = lkey<PB>(hk, q);
+            const uint64_t ks = kb < ka ? ka : kb;  // the upper end is the saddle
+            if (tabled)
+                insert((ks << (2 * ZB)) | min(za, zb) | ((uint64_t)max(za, zb) << ZB), za, zb);
+            else
+                lds_merge<VOL>(TL, hk, mh, za, ks, zb, cnt, cap, err);
         }
     }
     __syncthreads();
@@ -606,6 +602,7 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
         const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
         if (!valid(lx, ly, lz)) continue;
         uint32_t x = zl[p];
+        if (x >= cnt) { err |= ST_CORRUPT; continue; }
         const uint64_t level = lkey<PB>(hk, p);
         for (uint32_t step = 0; step < cap; ++step) {
             const uint64_t t = TL[x];
