@@ -38,7 +38,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 # key) the kernels pass on to each other.
 ALGO_BYTES_PER_VERTEX = {
     "k_local": 8,        # read f, write the local-basin label
-    "k_cross": 0,        # face edges only (per-minimum term below)
+    "k_cross": 0,        # per-face-edge and per-fact terms below
     "k_merge_q": 0,      # per-fact and per-minimum terms below
     "k_repair_min": 0,   # per-minimum term below
     "k_repair_reg": 16,  # read label and f, write the triplet
@@ -47,17 +47,31 @@ ALGO_BYTES_PER_VERTEX = {
 }
 
 
-def algo_bytes(kernel: str, n_vertices: int, n_pairs: int, n_local_minima: int, n_facts: int = 0) -> float:
+def algo_bytes(kernel: str, n_vertices: int, n_pairs: int, n_local_minima: int, n_facts: int = 0,
+               n_face_edges: int = 0) -> float:
     b = ALGO_BYTES_PER_VERTEX[kernel] * n_vertices
     if kernel == "k_merge_q":
         b += 16 * n_facts + 16 * n_local_minima  # read every queued fact, settle every slot
     if kernel == "k_local":
         b += 24 * n_local_minima   # write slot + key of every local minimum
-    if kernel in ("k_cross", "k_repair_min"):
+    if kernel == "k_cross":
+        b += 16 * n_face_edges + 16 * n_facts  # label + value of both ends, one fact out
+    if kernel == "k_repair_min":
         b += 16 * n_local_minima   # read (and rewrite) every slot once
     if kernel == "k_pairs_write":
         b += 16 * n_pairs          # birth, death ids and values
     return float(b)
+
+
+def face_edges(shape, mt) -> int:
+    """Grid edges that cross a tile face under the active tile shape of the
+    field's dims class."""
+    nx, ny, nz = mt.grid_dims(shape)
+    cls = 0 if nz > 1 else (1 if ny > 1 else 2)
+    sh = {s["id"]: s for s in mt.tile_shapes()}[mt.get_tile_shape(cls)]
+    tx, ty, tz = sh["tx"], sh["ty"], sh["tz"]
+    cut = lambda n, t: (n + t - 1) // t - 1  # interior tile boundaries along one axis
+    return cut(nx, tx) * ny * nz + cut(ny, ty) * nx * nz + cut(nz, tz) * nx * ny
 
 
 def src_hash() -> str:
@@ -380,9 +394,10 @@ def main():
     N = s.N
 
     n_min, n_facts = s.build_stats()  # local minima records and queued cross-tile facts (untimed)
+    n_face = face_edges(f.shape, mt)
     dom = max((k for k in kstats if k in ALGO_BYTES_PER_VERTEX), key=lambda k: kstats[k][0])
     avg_s = kstats[dom][0] / kstats[dom][1] / 1e3
-    ab = algo_bytes(dom, N, P, n_min, n_facts)
+    ab = algo_bytes(dom, N, P, n_min, n_facts, n_face)
     achieved = ab / avg_s / 1e9
     traffic = stored_traffic(dom, args.workload)
     roofline = {
@@ -397,7 +412,7 @@ def main():
         "algo_bytes_per_launch": ab,
     }
     per_kernel = {k: {"avg_ms": v[0] / v[1], "launches": v[1]} for k, v in sorted(kstats.items())}
-    path_bytes = sum(algo_bytes(k, N, P, n_min, n_facts) for k in ALGO_BYTES_PER_VERTEX)
+    path_bytes = sum(algo_bytes(k, N, P, n_min, n_facts, n_face) for k in ALGO_BYTES_PER_VERTEX)
 
     out = {
         "metric": "Mvertices/s merge tree+pairs (bit-exact), batched vs plain; %HBM peak; bwd μs",
@@ -414,7 +429,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "shape": list(f.shape), "vertices": N, "connectivity": 6,
                    "pairs": P, "roots": R, "tile_local_minima": n_min,
-                   "cross_tile_facts": n_facts},
+                   "cross_tile_facts": n_facts, "tile_face_edges": n_face},
         "roofline": roofline,
         "path_algo_GBps": path_bytes / dt / 1e9,
         "kernels": per_kernel,
