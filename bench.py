@@ -39,6 +39,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 ALGO_BYTES_PER_VERTEX = {
     "k_local": 8,        # read f, write the local-basin label
     "k_cross": 0,        # per-face-edge and per-fact terms below
+    "k_qscatter": 0,     # per-fact term below
     "k_merge_q": 0,      # per-fact and per-minimum terms below
     "k_repair_min": 0,   # per-minimum term below
     "k_repair_reg": 16,  # read label and f, write the triplet
@@ -50,6 +51,8 @@ ALGO_BYTES_PER_VERTEX = {
 def algo_bytes(kernel: str, n_vertices: int, n_pairs: int, n_local_minima: int, n_facts: int = 0,
                n_face_edges: int = 0) -> float:
     b = ALGO_BYTES_PER_VERTEX[kernel] * n_vertices
+    if kernel == "k_qscatter":
+        b += 32 * n_facts          # every fact read from the queue and written to its bin
     if kernel == "k_merge_q":
         b += 16 * n_facts + 16 * n_local_minima  # read every queued fact, settle every slot
     if kernel == "k_local":

@@ -67,7 +67,7 @@ static void with_shape(int id, F &&fn)
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t D, tfield, tstart, cs, pcnt, lbl, slot, mkey, queue, total;
+    size_t D, tfield, tstart, cs, pcnt, lbl, slot, mkey, queue, qbin, qhist, qtot, total;
 };
 
 struct ClassLaunch {
@@ -194,6 +194,9 @@ static int make_plan(const int64_t *dims, int32_t nf, Plan &p, const int *shape_
     L.slot = o; o = align256(o + sizeof(Slot) * mcap);
     L.mkey = o; o = align256(o + sizeof(uint64_t) * mcap);
     L.queue = o; o = align256(o + sizeof(Fact) * p.q_cap * 8);
+    L.qbin = o; o = align256(o + sizeof(Fact) * p.q_cap * 8);
+    L.qhist = o; o = align256(o + sizeof(uint32_t) * kQCounters * 8);
+    L.qtot = o; o = align256(o + sizeof(uint32_t) * kQScanBlocks * 8);
     L.total = o;
     return MT_OK;
 }
@@ -206,7 +209,8 @@ struct Ptrs {
     uint32_t *pcnt, *lbl;
     Slot *slot;
     uint64_t *mkey;
-    Fact *queue;
+    Fact *queue, *qbin;
+    uint32_t *qhist, *qtot;
 };
 
 static Ptrs ws_ptrs(const Plan &p, void *ws)
@@ -224,6 +228,9 @@ static Ptrs ws_ptrs(const Plan &p, void *ws)
     w.slot = (Slot *)(b + L.slot);
     w.mkey = (uint64_t *)(b + L.mkey);
     w.queue = (Fact *)(b + L.queue);
+    w.qbin = (Fact *)(b + L.qbin);
+    w.qhist = (uint32_t *)(b + L.qhist);
+    w.qtot = (uint32_t *)(b + L.qtot);
     return w;
 }
 
@@ -325,7 +332,7 @@ static int launch_cross(const Plan &p, const ClassLaunch &cl, const Ptrs &w, con
     MT_LAUNCH("k_cross", HIP_KERNEL_NAME(k_cross<S>), dim3((unsigned)cl.ntiles), dim3(S::NT), st, f,
               (const uint32_t *)w.lbl, w.queue, (uint32_t)p.q_cap, (const FieldDesc *)w.D,
               (const int32_t *)w.tfield + cl.cb, (const int64_t *)w.tstart + cl.cb, cl.nfc, cl.tile0, cl.ntiles,
-              g_remap, w.h);
+              g_remap, w.qhist, w.h);
     return MT_OK;
 }
 
@@ -334,6 +341,8 @@ static int enqueue_build(const Plan &p, const Ptrs &w, const float *f, uint64_t 
 {
     const int nf = (int)p.d.size();
     const uint32_t n = (uint32_t)p.n_total;
+    MT_LAUNCH("k_zero32", k_zero32, dim3(kQCounters * 8 / kBlock), dim3(kBlock), st, w.qhist,
+              (int64_t)kQCounters * 8);
     for (int c = 0; c < 3; ++c) {
         const ClassLaunch &cl = p.cls[c];
         if (cl.ntiles == 0) continue;
@@ -348,8 +357,15 @@ static int enqueue_build(const Plan &p, const Ptrs &w, const float *f, uint64_t 
         with_shape(cl.shape, [&](auto s) { rc = launch_cross<decltype(s)>(p, cl, w, f, st); });
         if (rc != MT_OK) return rc;
     }
+    // facts into ascending order of their saddle's key bin, per XCD queue
     const unsigned gq = 8 * (unsigned)std::min<int64_t>(2048, std::max<int64_t>(1, (p.q_cap + kBlock - 1) / kBlock));
-    MT_LAUNCH("k_merge_q", k_merge_q, dim3(gq), dim3(kBlock), st, f, (const Fact *)w.queue, (uint32_t)p.q_cap, w.slot,
+    MT_LAUNCH("k_qtotals", k_qtotals, dim3(kQScanBlocks, 8), dim3(kQScanThreads), st, (const uint32_t *)w.qhist,
+              w.qtot);
+    MT_LAUNCH("k_qscan", k_qscan, dim3(kQScanBlocks, 8), dim3(kQScanThreads), st, w.qhist,
+              (const uint32_t *)w.qtot);
+    MT_LAUNCH("k_qscatter", k_qscatter, dim3(gq), dim3(kBlock), st, (const Fact *)w.queue, w.qbin,
+              (uint32_t)p.q_cap, w.qhist, w.h);
+    MT_LAUNCH("k_merge_q", k_merge_q, dim3(gq), dim3(kBlock), st, f, (const Fact *)w.qbin, (uint32_t)p.q_cap, w.slot,
               (const uint64_t *)w.mkey, n, g_cap, w.h);
     const unsigned gm = (unsigned)std::min<int64_t>(8192, std::max<int64_t>(1, (p.m_cap + kBlock - 1) / kBlock));
     MT_LAUNCH("k_repair_min", k_repair_min, dim3(gm), dim3(kBlock), st, f, w.slot, n, g_cap, w.h);

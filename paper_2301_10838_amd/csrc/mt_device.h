@@ -70,6 +70,19 @@ constexpr int kBlock = 256;                  // threads per workgroup of the fla
 constexpr int kChunk = 4096;                 // vertices per workgroup in flat passes
 constexpr int kSetupMax = 12;                // field descriptors per k_setup launch
 constexpr int kBwdGroup = 64;                // fields per backward launch
+// Cross-tile facts are binned by the top bits of their saddle key.  Each
+// bin's counter has kQCopies copies (chosen by the fact's queue position, so
+// the counting and the scattering pass agree), which keeps the atomics on
+// one bin apart.
+constexpr int kQBinBits = 14;
+constexpr int kQBins = 1 << kQBinBits;
+constexpr int kQCopies = 16;
+constexpr int kQChunkBits = 10;              // queue positions per copy turn
+constexpr int kQCounters = kQBins * kQCopies;  // per XCD
+__host__ __device__ constexpr uint32_t qcounter(uint32_t pos, uint64_t ks)
+{
+    return (((pos >> kQChunkBits) % kQCopies) << kQBinBits) | (uint32_t)(ks >> (64 - kQBinBits));
+}
 
 constexpr uint32_t ST_NAN = 1u, ST_LIVELOCK = 2u, ST_CAPACITY = 4u, ST_CORRUPT = 8u;
 
@@ -673,7 +686,8 @@ __global__ __launch_bounds__(S::NT) void k_cross(const float *__restrict__ f, co
                                                  Fact *__restrict__ queue, uint32_t qsub,
                                                  const FieldDesc *__restrict__ D, const int32_t *__restrict__ tfield,
                                                  const int64_t *__restrict__ tstart, int nfc, int64_t tile0,
-                                                 int64_t ntiles, int remap, Header *__restrict__ h)
+                                                 int64_t ntiles, int remap, uint32_t *__restrict__ qhist,
+                                                 Header *__restrict__ h)
 {
     constexpr int TX = S::TX, TY = S::TY, TZ = S::TZ, NT = S::NT;
     // faces that can have a neighbour: a 2-D shape has no z face, a 1-D one no y face
@@ -757,9 +771,14 @@ __global__ __launch_bounds__(S::NT) void k_cross(const float *__restrict__ f, co
     uint32_t pos = sbase + incl - mine;
     for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) pos += wsum[w];
     Fact *__restrict__ mq = queue + (size_t)(blockIdx.x % 8) * qsub;
+    uint32_t *__restrict__ hist = qhist + (size_t)(blockIdx.x % 8) * kQCounters;
     auto put = [&](const Fact &q) {
-        if (pos < qsub) mq[pos] = q;
-        else err |= ST_CORRUPT;  // cannot happen: each queue holds every face edge of its tiles
+        if (pos < qsub) {
+            mq[pos] = q;
+            atomicAdd(hist + qcounter(pos, q.ks), 1u);
+        } else {
+            err |= ST_CORRUPT;  // cannot happen: each queue holds every face edge of its tiles
+        }
         ++pos;
     };
     for (int i = 0; i < nover; ++i) put(over[i]);
@@ -768,6 +787,102 @@ __global__ __launch_bounds__(S::NT) void k_cross(const float *__restrict__ f, co
         if (key != ~0ull) put(Fact{lo32(key), hi32(key), hbest[i]});
     }
     if (err) atomicOr(&h->status, err);
+}
+
+// Cross-tile facts in ascending order of their saddle key's top bits (a
+// counting sort per XCD queue).  Any order of the merges gives the same tree;
+// in this one most merges find the higher minimum still a root at their level,
+// so few links are displaced and few swaps collide.
+__global__ void k_zero32(uint32_t *__restrict__ p, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+// Exclusive scan of each XCD's counters in (bin, copy) order, in two
+// launches over kQScanBlocks workgroups per XCD: block totals first, then
+// each block scans its bins from the sum of the blocks before it.  Lane t of
+// a block owns QB bins with all their copies.
+constexpr int kQScanBlocks = 32;
+constexpr int kQScanThreads = 256;
+constexpr int kQBinsPerBlock = kQBins / kQScanBlocks;
+static_assert(kQBinsPerBlock % kQScanThreads == 0, "whole bins per lane");
+
+__device__ __forceinline__ uint32_t block_sum(uint32_t v, uint32_t *wsum)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = v;
+    __syncthreads();
+    uint32_t t = 0;
+    for (int w = 0; w < kQScanThreads / 64; ++w) t += wsum[w];
+    return t;
+}
+
+// grid (kQScanBlocks, 8): total of every block's counters
+__global__ __launch_bounds__(kQScanThreads) void k_qtotals(const uint32_t *__restrict__ qhist,
+                                                          uint32_t *__restrict__ qtot)
+{
+    constexpr int QB = kQBinsPerBlock / kQScanThreads;
+    __shared__ uint32_t wsum[kQScanThreads / 64];
+    const uint32_t *__restrict__ hist = qhist + (size_t)blockIdx.y * kQCounters + blockIdx.x * kQBinsPerBlock;
+    uint32_t run = 0;
+    for (int c = 0; c < kQCopies; ++c)
+#pragma unroll
+        for (int b = 0; b < QB; ++b) run += hist[(c << kQBinBits) + b * kQScanThreads + threadIdx.x];
+    const uint32_t t = block_sum(run, wsum);
+    if (threadIdx.x == 0) qtot[blockIdx.y * kQScanBlocks + blockIdx.x] = t;
+}
+
+// grid (kQScanBlocks, 8): counters -> exclusive prefix in (bin, copy) order
+__global__ __launch_bounds__(kQScanThreads) void k_qscan(uint32_t *__restrict__ qhist,
+                                                        const uint32_t *__restrict__ qtot)
+{
+    constexpr int QB = kQBinsPerBlock / kQScanThreads;
+    __shared__ uint32_t wsum[kQScanThreads / 64];
+    uint32_t *__restrict__ hist = qhist + (size_t)blockIdx.y * kQCounters + blockIdx.x * kQBinsPerBlock;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    uint32_t base = 0;
+    for (int j = 0; j < (int)blockIdx.x; ++j) base += qtot[blockIdx.y * kQScanBlocks + j];
+    // lane t owns bins t * QB .. t * QB + QB - 1 of the block
+    uint32_t run = 0;
+#pragma unroll
+    for (int b = 0; b < QB; ++b)
+        for (int c = 0; c < kQCopies; ++c) run += hist[(c << kQBinBits) + t * QB + b];
+    uint32_t inc = run;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(inc, o);
+        if (lane >= o) inc += y;
+    }
+    if (lane == 63) wsum[wave] = inc;
+    __syncthreads();
+    uint32_t e = base + inc - run;
+    for (int w = 0; w < wave; ++w) e += wsum[w];
+#pragma unroll
+    for (int b = 0; b < QB; ++b)
+        for (int c = 0; c < kQCopies; ++c) {
+            uint32_t *const q = hist + (c << kQBinBits) + t * QB + b;
+            const uint32_t v = *q;
+            *q = e;
+            e += v;
+        }
+}
+
+// Each fact to its counter's next free place; workgroup b serves XCD b % 8.
+__global__ __launch_bounds__(kBlock) void k_qscatter(const Fact *__restrict__ queue, Fact *__restrict__ qbin,
+                                                     uint32_t qsub, uint32_t *__restrict__ qhist,
+                                                     const Header *__restrict__ h)
+{
+    const uint32_t x = blockIdx.x % 8, per = gridDim.x / 8;
+    const uint32_t Q = min(h->n_cross[x], qsub);
+    const Fact *__restrict__ src = queue + (size_t)x * qsub;
+    Fact *__restrict__ dst = qbin + (size_t)x * qsub;
+    uint32_t *__restrict__ hist = qhist + (size_t)x * kQCounters;
+    for (uint32_t i = (blockIdx.x / 8) * kBlock + threadIdx.x; i < Q; i += per * kBlock) {
+        const Fact q = src[i];
+        const uint32_t at = atomicAdd(hist + qcounter(i, q.ks), 1u);
+        if (at < Q) dst[at] = q;  // always: the counters count exactly the queued facts
+    }
 }
 
 // Merge of the queued cross-tile facts, one per lane; workgroup b serves the
