@@ -667,6 +667,36 @@ __device__ void gmerge(Slot *__restrict__ S, const uint64_t *__restrict__ mkey, 
     err |= ST_LIVELOCK;
 }
 
+// Per-workgroup aggregation of bin-counter increments: lanes add into a
+// small LDS table keyed by counter index (the returned rank is the lane's
+// place among the workgroup's facts of that counter); flush adds each
+// distinct counter's total to the global counters once.  A counter that finds
+// no table room is counted in global memory directly (rank ~0u).
+template <int LH>
+struct CounterAgg {
+    uint32_t key[LH], cnt[LH], base[LH];
+    __device__ void clear(int tid, int nt)
+    {
+        for (int i = tid; i < LH; i += nt) { key[i] = 0xffffffffu; cnt[i] = 0u; }
+    }
+    // returns the rank of this increment within its counter, or ~0u if not tabled
+    __device__ uint32_t add(uint32_t k, uint32_t &slot)
+    {
+        uint32_t si = (k * 0x9E3779B1u) >> (32 - __builtin_ctz(LH));
+        for (int probe = 0; probe < 16; ++probe) {
+            uint32_t prev = 0xffffffffu;
+            __hip_atomic_compare_exchange_strong(key + si, &prev, k, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (prev == 0xffffffffu || prev == k) {
+                slot = si;
+                return atomicAdd(cnt + si, 1u);
+            }
+            si = (si + 1) & (LH - 1);
+        }
+        return 0xffffffffu;
+    }
+};
+
 constexpr int pow2_at_least(int v)
 {
     int p = 1;
@@ -698,11 +728,13 @@ __global__ __launch_bounds__(S::NT) void k_cross(const float *__restrict__ f, co
     __shared__ uint64_t hbest[H];  // lowest upper-end key of an edge joining that pair
     __shared__ uint32_t wsum[NT / 64];
     __shared__ uint32_t sbase;
+    __shared__ CounterAgg<512> agg;
     const int64_t tl = xcd_tile(blockIdx.x, gridDim.x, remap);
     if (tl >= ntiles) return;
     const TileCtx c = tile_ctx<S>(D, tfield, tstart, nfc, tile0 + tl);
     const uint32_t off = (uint32_t)c.d.offset;
     const bool hx = c.x0 + TX < c.d.nx, hy = c.y0 + TY < c.d.ny, hz = c.z0 + TZ < c.d.nz;
+    agg.clear(threadIdx.x, NT);
     const uint32_t M = h->n_minima;
     for (int i = threadIdx.x; i < H; i += NT) {
         hpair[i] = ~0ull;
@@ -775,7 +807,9 @@ __global__ __launch_bounds__(S::NT) void k_cross(const float *__restrict__ f, co
     auto put = [&](const Fact &q) {
         if (pos < qsub) {
             mq[pos] = q;
-            atomicAdd(hist + qcounter(pos, q.ks), 1u);
+            const uint32_t k = qcounter(pos, q.ks);
+            uint32_t slot;
+            if (agg.add(k, slot) == 0xffffffffu) atomicAdd(hist + k, 1u);
         } else {
             err |= ST_CORRUPT;  // cannot happen: each queue holds every face edge of its tiles
         }
@@ -786,6 +820,9 @@ __global__ __launch_bounds__(S::NT) void k_cross(const float *__restrict__ f, co
         const uint64_t key = hpair[i];
         if (key != ~0ull) put(Fact{lo32(key), hi32(key), hbest[i]});
     }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 512; i += NT)
+        if (agg.cnt[i]) atomicAdd(hist + agg.key[i], agg.cnt[i]);
     if (err) atomicOr(&h->status, err);
 }
 
@@ -868,20 +905,39 @@ __global__ __launch_bounds__(kQScanThreads) void k_qscan(uint32_t *__restrict__ 
         }
 }
 
-// Each fact to its counter's next free place; workgroup b serves XCD b % 8.
+// Each fact to its counter's next free place; workgroup b serves XCD b % 8
+// and takes kBlock consecutive facts at a time, reserving one range per
+// distinct counter.
 __global__ __launch_bounds__(kBlock) void k_qscatter(const Fact *__restrict__ queue, Fact *__restrict__ qbin,
                                                      uint32_t qsub, uint32_t *__restrict__ qhist,
                                                      const Header *__restrict__ h)
 {
+    __shared__ CounterAgg<2 * kBlock> agg;
     const uint32_t x = blockIdx.x % 8, per = gridDim.x / 8;
     const uint32_t Q = min(h->n_cross[x], qsub);
     const Fact *__restrict__ src = queue + (size_t)x * qsub;
     Fact *__restrict__ dst = qbin + (size_t)x * qsub;
     uint32_t *__restrict__ hist = qhist + (size_t)x * kQCounters;
-    for (uint32_t i = (blockIdx.x / 8) * kBlock + threadIdx.x; i < Q; i += per * kBlock) {
-        const Fact q = src[i];
-        const uint32_t at = atomicAdd(hist + qcounter(i, q.ks), 1u);
-        if (at < Q) dst[at] = q;  // always: the counters count exactly the queued facts
+    for (uint32_t i0 = (blockIdx.x / 8) * kBlock; i0 < Q; i0 += per * kBlock) {  // uniform per workgroup
+        agg.clear(threadIdx.x, kBlock);
+        __syncthreads();
+        const uint32_t i = i0 + threadIdx.x;
+        Fact q{};
+        uint32_t k = 0, slot = 0, rank = 0;
+        if (i < Q) {
+            q = src[i];
+            k = qcounter(i, q.ks);
+            rank = agg.add(k, slot);
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < 2 * kBlock; e += kBlock)
+            if (agg.cnt[e]) agg.base[e] = atomicAdd(hist + agg.key[e], agg.cnt[e]);
+        __syncthreads();
+        if (i < Q) {
+            const uint32_t at = rank != 0xffffffffu ? agg.base[slot] + rank : atomicAdd(hist + k, 1u);
+            if (at < Q) dst[at] = q;  // always: the counters count exactly the queued facts
+        }
+        __syncthreads();
     }
 }
 
