@@ -67,7 +67,7 @@ static void with_shape(int id, F &&fn)
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t D, tfield, tstart, cs, pcnt, lbl, slot, mkey, queue, qbin, qhist, qtot, total;
+    size_t D, tfield, tstart, cs, pcnt, lbl, slot, mkey, queue, qbin, qhist, qtot, xface, total;
 };
 
 struct ClassLaunch {
@@ -197,6 +197,7 @@ static int make_plan(const int64_t *dims, int32_t nf, Plan &p, const int *shape_
     L.qbin = o; o = align256(o + sizeof(Fact) * p.q_cap * 8);
     L.qhist = o; o = align256(o + sizeof(uint32_t) * kQCounters * 8);
     L.qtot = o; o = align256(o + sizeof(uint32_t) * kQScanBlocks * 8);
+    L.xface = o; o = align256(o + sizeof(uint64_t) * 2 * kXFace * p.n_tiles);
     L.total = o;
     return MT_OK;
 }
@@ -211,6 +212,7 @@ struct Ptrs {
     uint64_t *mkey;
     Fact *queue, *qbin;
     uint32_t *qhist, *qtot;
+    uint64_t *xface;
 };
 
 static Ptrs ws_ptrs(const Plan &p, void *ws)
@@ -231,6 +233,7 @@ static Ptrs ws_ptrs(const Plan &p, void *ws)
     w.qbin = (Fact *)(b + L.qbin);
     w.qhist = (uint32_t *)(b + L.qhist);
     w.qtot = (uint32_t *)(b + L.qtot);
+    w.xface = (uint64_t *)(b + L.xface);
     return w;
 }
 
@@ -322,7 +325,7 @@ static int launch_local(const Plan &p, const ClassLaunch &cl, const Ptrs &w, con
 {
     MT_LAUNCH("k_local", HIP_KERNEL_NAME(k_local<S>), dim3((unsigned)cl.ntiles), dim3(S::NT), st, f, w.lbl, w.slot,
               w.mkey, (const FieldDesc *)w.D, (const int32_t *)w.tfield + cl.cb, (const int64_t *)w.tstart + cl.cb,
-              cl.nfc, cl.tile0, cl.ntiles, g_remap, (uint32_t)p.m_cap, g_cap, w.h);
+              cl.nfc, cl.tile0, cl.ntiles, g_remap, (uint32_t)p.m_cap, g_cap, w.xface, w.h);
     return MT_OK;
 }
 
@@ -332,7 +335,7 @@ static int launch_cross(const Plan &p, const ClassLaunch &cl, const Ptrs &w, con
     MT_LAUNCH("k_cross", HIP_KERNEL_NAME(k_cross<S>), dim3((unsigned)cl.ntiles), dim3(S::NT), st, f,
               (const uint32_t *)w.lbl, w.queue, (uint32_t)p.q_cap, (const FieldDesc *)w.D,
               (const int32_t *)w.tfield + cl.cb, (const int64_t *)w.tstart + cl.cb, cl.nfc, cl.tile0, cl.ntiles,
-              g_remap, w.qhist, w.h);
+              g_remap, w.qhist, (const uint64_t *)w.xface, w.h);
     return MT_OK;
 }
 

@@ -70,6 +70,7 @@ constexpr int kBlock = 256;                  // threads per workgroup of the fla
 constexpr int kChunk = 4096;                 // vertices per workgroup in flat passes
 constexpr int kSetupMax = 12;                // field descriptors per k_setup launch
 constexpr int kBwdGroup = 64;                // fields per backward launch
+constexpr int kXFace = 256;                  // largest x face of a tile shape (TY * TZ)
 // Cross-tile facts are binned by the top bits of their saddle key.  Each
 // bin's counter has kQCopies copies (chosen by the fact's queue position, so
 // the counting and the scattering pass agree), which keeps the atomics on
@@ -346,9 +347,10 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
                                                  const FieldDesc *__restrict__ D, const int32_t *__restrict__ tfield,
                                                  const int64_t *__restrict__ tstart, int nfc, int64_t tile0,
                                                  int64_t ntiles, int remap, uint32_t mcap, uint32_t cap,
-                                                 Header *__restrict__ h)
+                                                 uint64_t *__restrict__ xface, Header *__restrict__ h)
 {
     constexpr int NT = S::NT, VOL = S::VOL, TX = S::TX, TY = S::TY;
+    static_assert(S::TY * S::TZ <= kXFace, "x face record");
     constexpr int HALF = VOL / 2;   // local minima are pairwise non-adjacent: at most half the tile
     using L = LTrip<VOL>;
     constexpr int PB = L::PB;
@@ -625,6 +627,10 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
             x = v;
         }
         lbl[gid(p)] = b0 + x;
+        // the first and last x columns also go to the tile's face record
+        // (order key << 32 | label), read contiguously by the cross pass
+        if (lx == 0 || lx == TX - 1)
+            xface[((size_t)c.t * 2 + (lx != 0)) * kXFace + ly + TY * lz] = ((uint64_t)hk[p] << 32) | (b0 + x);
     }
     if (err) atomicOr(&h->status, err);
 }
@@ -717,7 +723,7 @@ __global__ __launch_bounds__(S::NT) void k_cross(const float *__restrict__ f, co
                                                  const FieldDesc *__restrict__ D, const int32_t *__restrict__ tfield,
                                                  const int64_t *__restrict__ tstart, int nfc, int64_t tile0,
                                                  int64_t ntiles, int remap, uint32_t *__restrict__ qhist,
-                                                 Header *__restrict__ h)
+                                                 const uint64_t *__restrict__ xface, Header *__restrict__ h)
 {
     constexpr int TX = S::TX, TY = S::TY, TZ = S::TZ, NT = S::NT;
     // faces that can have a neighbour: a 2-D shape has no z face, a 1-D one no y face
@@ -762,9 +768,19 @@ __global__ __launch_bounds__(S::NT) void k_cross(const float *__restrict__ f, co
         if (!ok || lx >= c.ex || ly >= c.ey || lz >= c.ez) continue;
         const uint32_t a = off + (uint32_t)((c.x0 + lx) + (int64_t)c.d.nx * (c.y0 + ly) + c.sxy * (c.z0 + lz));
         const uint32_t b = a + (uint32_t)step;
-        const uint32_t za = lbl[a], zb = lbl[b];
+        uint32_t za, zb;
+        uint64_t ka, kb;
+        if (e < FX) {  // x face: this tile's last column and the next tile's first, from the face records
+            const uint64_t ra = xface[((size_t)c.t * 2 + 1) * kXFace + e];
+            const uint64_t rb = xface[((size_t)(c.t + 1) * 2) * kXFace + e];
+            za = lo32(ra); zb = lo32(rb);
+            ka = (ra & 0xffffffff00000000ull) | a;
+            kb = (rb & 0xffffffff00000000ull) | b;
+        } else {
+            za = lbl[a]; zb = lbl[b];
+            ka = vkey(f, a); kb = vkey(f, b);
+        }
         if (za >= M || zb >= M) { err |= ST_CORRUPT; continue; }
-        const uint64_t ka = vkey(f, a), kb = vkey(f, b);
         const uint64_t ks = kb < ka ? ka : kb;  // the upper end is the saddle
         const uint64_t key = (uint64_t)min(za, zb) | ((uint64_t)max(za, zb) << 32);
         uint32_t si = (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> (64 - __builtin_ctz(H)));
