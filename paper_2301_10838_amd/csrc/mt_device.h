@@ -1016,9 +1016,12 @@ __global__ __launch_bounds__(kBlock) void k_repair_min(const float *__restrict__
 // Output triplets in vertex order, field-local ids.  A local minimum copies
 // its own (repaired) triplet; any other vertex u gets (u, u, representative
 // of its local minimum at the level of u).  Also counts pairs and roots per
-// chunk.
+// chunk.  Slots are read-only here, so plain loads; each lane carries RV
+// vertices at once, so the dependent loads of their chases (label -> slot ->
+// slot ... -> minimum key) overlap.
+constexpr int RV = 4;
 __global__ __launch_bounds__(kBlock) void k_repair_reg(const float *__restrict__ f, const uint32_t *__restrict__ lbl,
-                                                       Slot *__restrict__ S, const uint64_t *__restrict__ mkey,
+                                                       const Slot *__restrict__ S, const uint64_t *__restrict__ mkey,
                                                        uint64_t *__restrict__ T, uint32_t *__restrict__ pcnt,
                                                        const FieldDesc *__restrict__ D, const int64_t *__restrict__ cs,
                                                        int nf, uint32_t n, uint32_t cap, Header *__restrict__ h)
@@ -1031,32 +1034,94 @@ __global__ __launch_bounds__(kBlock) void k_repair_reg(const float *__restrict__
     const uint32_t off = (uint32_t)d.offset;
     const uint32_t M = h->n_minima;
     uint32_t err = 0, np = 0, nr = 0;
-    for (int64_t j = lo + threadIdx.x; j < hi; j += kBlock) {
-        const uint32_t u = off + (uint32_t)j;
-        const uint32_t z = lbl[u];
-        if (z >= M) { err |= ST_CORRUPT; continue; }
-        // everything that depends only on z, in one trip
-        const uint64_t mz = mkey[z];
-        const SlotRead t = ld_slot(S, z);
-        const uint32_t s0 = lo32(t.w), v0 = hi32(t.w);
-        if (v0 >= M || s0 >= n) { err |= ST_CORRUPT; continue; }
-        uint32_t s, gr;
-        if (lo32(mz) == u) {  // u is a local minimum: its own repaired triplet
-            s = s0;
-            np += (s0 != u);
-            nr += (v0 == z);
-            gr = v0 == z ? u : lo32(mkey[v0]);
-        } else {              // (u, u, representative of z at the level of u)
-            s = u;
-            const uint64_t level = vkey(f, u);
-            if (v0 == z || saddle_key(t, f) > level) {
-                gr = lo32(mz);
-            } else {
-                gr = lo32(mkey[chase(S, f, M, n, v0, level, cap, err)]);
+    static_assert(kChunk % (kBlock * RV) == 0, "whole groups per chunk");
+    for (int64_t g0 = lo; g0 < hi; g0 += kBlock * RV) {
+        uint32_t u[RV], z[RV], x[RV], s[RV], gr[RV];
+        uint64_t level[RV], mz[RV], tw[RV], tk[RV];
+        uint32_t live = 0, act = 0, need = 0;  // bit i: vertex i is written / chasing / needs mkey[x[i]]
+#pragma unroll
+        for (int i = 0; i < RV; ++i) {
+            const int64_t j = g0 + i * kBlock + threadIdx.x;
+            const bool in = j < hi;
+            live |= (uint32_t)in << i;
+            u[i] = off + (uint32_t)(in ? j : lo);
+            z[i] = lbl[u[i]];
+            level[i] = vkey(f, u[i]);
+        }
+#pragma unroll
+        for (int i = 0; i < RV; ++i) {
+            if (z[i] >= M) {
+                if ((live >> i) & 1u) err |= ST_CORRUPT;
+                z[i] = 0;
+                live &= ~(1u << i);
+            }
+            mz[i] = mkey[z[i]];
+            tw[i] = S[z[i]].w;
+            tk[i] = S[z[i]].k;
+        }
+#pragma unroll
+        for (int i = 0; i < RV; ++i) {
+            x[i] = z[i];
+            s[i] = u[i];
+            gr[i] = u[i];
+            const uint32_t s0 = lo32(tw[i]), v0 = hi32(tw[i]);
+            if (v0 >= M || s0 >= n) {
+                if ((live >> i) & 1u) err |= ST_CORRUPT;
+                live &= ~(1u << i);
+                continue;
+            }
+            const uint64_t sk = lo32(tk[i]) == s0 ? tk[i] : vkey(f, s0);
+            if (lo32(mz[i]) == u[i]) {  // u is a local minimum: its own repaired triplet
+                s[i] = s0;
+                if ((live >> i) & 1u) {
+                    np += (s0 != u[i]);
+                    nr += (v0 == z[i]);
+                }
+                if (v0 != z[i]) {
+                    x[i] = v0;
+                    need |= 1u << i;
+                }
+            } else if (v0 == z[i] || sk > level[i]) {
+                gr[i] = lo32(mz[i]);
+            } else {                    // (u, u, representative of z at the level of u)
+                x[i] = v0;
+                act |= 1u << i;
+                need |= 1u << i;
             }
         }
-        if (gr >= n) { err |= ST_CORRUPT; continue; }
-        T[u] = pack(s - off, gr - off);
+        for (uint32_t step = 0; act != 0; ++step) {
+            if (step == cap) { err |= ST_LIVELOCK; break; }
+#pragma unroll
+            for (int i = 0; i < RV; ++i) {
+                if (!((act >> i) & 1u)) continue;
+                tw[i] = S[x[i]].w;
+                tk[i] = S[x[i]].k;
+            }
+#pragma unroll
+            for (int i = 0; i < RV; ++i) {
+                if (!((act >> i) & 1u)) continue;
+                const uint32_t v = hi32(tw[i]), sv = lo32(tw[i]);
+                if (v >= M || sv >= n) {
+                    err |= ST_CORRUPT;
+                    act &= ~(1u << i);
+                    need &= ~(1u << i);
+                    live &= ~(1u << i);
+                    continue;
+                }
+                const uint64_t sk = lo32(tk[i]) == sv ? tk[i] : vkey(f, sv);
+                if (v == x[i] || sk > level[i]) act &= ~(1u << i);
+                else x[i] = v;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < RV; ++i)
+            if ((need >> i) & 1u) gr[i] = lo32(mkey[x[i]]);
+#pragma unroll
+        for (int i = 0; i < RV; ++i) {
+            if (!((live >> i) & 1u)) continue;
+            if (gr[i] >= n) { err |= ST_CORRUPT; continue; }
+            T[u[i]] = pack(s[i] - off, gr[i] - off);
+        }
     }
     for (int o = 32; o > 0; o >>= 1) {
         np += __shfl_xor(np, o);
