@@ -484,17 +484,32 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
     const uint32_t cnt = scnt;
 
     // local basins: follow the pointers to the local minimum (keys fall
-    // strictly along them, so at most VOL steps)
-    for (int p = threadIdx.x; p < VOL; p += NT) {
-        const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
-        if (!valid(lx, ly, lz) || wl[p] == p) continue;
-        int x = p;
-        for (int step = 0; step < VOL; ++step) {
-            const int y = wl[x];
-            if (y == x) break;
-            x = y;
+    // strictly along them, so at most VOL steps); a lane follows the chains
+    // of all its vertices together so that their loads overlap
+    {
+        int xs[PER];
+        uint32_t act = 0;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int p = k * NT + threadIdx.x;
+            const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
+            xs[k] = p;
+            if (valid(lx, ly, lz) && wl[p] != p) act |= 1u << k;
         }
-        zl[p] = zl[x];
+        const uint32_t moved = act;
+        for (int step = 0; act != 0 && step < VOL; ++step) {
+            int ys[PER];
+#pragma unroll
+            for (int k = 0; k < PER; ++k) ys[k] = (act >> k) & 1u ? (int)wl[xs[k]] : xs[k];
+#pragma unroll
+            for (int k = 0; k < PER; ++k) {
+                if (ys[k] == xs[k]) act &= ~(1u << k);
+                xs[k] = ys[k];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < PER; ++k)
+            if ((moved >> k) & 1u) zl[k * NT + threadIdx.x] = zl[xs[k]];
     }
     __syncthreads();
     const uint32_t b0 = sb0;
