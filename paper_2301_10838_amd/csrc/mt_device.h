@@ -544,25 +544,34 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
         }
         lds_merge<VOL>(TL, hk, mh, za, val >> (2 * ZB), zb, cnt, cap, err);
     };
-    for (int p = threadIdx.x; p < VOL; p += NT) {
-        const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
-        const bool ok = valid(lx, ly, lz);
-        const uint32_t za = ok ? zl[p] : 0u;
-        const uint64_t ka = ok ? lkey<PB>(hk, p) : 0ull;
+    // A lane first marks which of its (vertex, direction) slots hold such an
+    // edge, then inserts one marked slot per round: a wave runs as many rounds
+    // as its busiest lane has edges, not one per slot.
+    static_assert(PER * 3 <= 32, "slot marks fit one word");
+    uint32_t pend = 0;
 #pragma unroll
-        for (int dir = 0; dir < 3; ++dir) {
-            const int q = p + (dir == 0 ? 1 : dir == 1 ? TX : TX * TY);
-            const bool edge = ok && (dir == 0 ? lx + 1 < c.ex : dir == 1 ? ly + 1 < c.ey : lz + 1 < c.ez);
-            if (!edge) continue;
-            const uint32_t zb = zl[q];
-            if (zb == za) continue;
-            const uint64_t kb = lkey<PB>(hk, q);
-            const uint64_t ks = kb < ka ? ka : kb;  // the upper end is the saddle
-            if (tabled)
-                insert((ks << (2 * ZB)) | min(za, zb) | ((uint64_t)max(za, zb) << ZB), za, zb);
-            else
-                lds_merge<VOL>(TL, hk, mh, za, ks, zb, cnt, cap, err);
-        }
+    for (int k = 0; k < PER; ++k) {
+        const int p = k * NT + threadIdx.x;
+        const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
+        if (!valid(lx, ly, lz)) continue;
+        const uint32_t za = zl[p];
+        if (lx + 1 < c.ex && zl[p + 1] != za) pend |= 1u << (3 * k);
+        if (ly + 1 < c.ey && zl[p + TX] != za) pend |= 1u << (3 * k + 1);
+        if (lz + 1 < c.ez && zl[p + TX * TY] != za) pend |= 1u << (3 * k + 2);
+    }
+    while (pend) {
+        const int b = __builtin_ctz(pend);
+        pend &= pend - 1;
+        const int k = b / 3, dir = b - 3 * k;
+        const int p = k * NT + threadIdx.x;
+        const int q = p + (dir == 0 ? 1 : dir == 1 ? TX : TX * TY);
+        const uint32_t za = zl[p], zb = zl[q];
+        const uint64_t ka = lkey<PB>(hk, p), kb = lkey<PB>(hk, q);
+        const uint64_t ks = kb < ka ? ka : kb;  // the upper end is the saddle
+        if (tabled)
+            insert((ks << (2 * ZB)) | min(za, zb) | ((uint64_t)max(za, zb) << ZB), za, zb);
+        else
+            lds_merge<VOL>(TL, hk, mh, za, ks, zb, cnt, cap, err);
     }
     __syncthreads();
     // Occupied entries, compacted to the front of the table so that every
