@@ -61,6 +61,17 @@ typedef enum {
     MT_ERR_INTERNAL = -8     /* a kernel met an out-of-range id (broken invariant); output invalid */
 } mt_status;
 
+/* Which tree: the merge (join) tree of sublevel sets, vertices ordered by
+ * (value, id) -- the paper's definition (Sec. 2) -- or the split tree of
+ * superlevel sets, the setting the paper's experiments report (Sec. 4): the
+ * merge tree of -f, vertices ordered by (-value, id).  For the split tree the
+ * triplets, pairs and minima below read "maxima"; pair values stay bit copies
+ * of f. */
+enum {
+    MT_TREE_MERGE = 0,
+    MT_TREE_SPLIT = 1
+};
+
 /* Human-readable name of a status code (static string). */
 const char *mt_status_string(int status);
 
@@ -97,6 +108,14 @@ size_t mt_batch_workspace_bytes(const int64_t *dims, int32_t n_fields);
  */
 int mt_build(const float *field, int64_t nx, int64_t ny, int64_t nz,
              uint32_t *triplets, void *workspace, size_t ws_bytes, void *stream);
+
+/*
+ * mt_build_tree -- mt_build for either tree: kind = MT_TREE_MERGE (the same
+ * as mt_build) or MT_TREE_SPLIT (the merge tree of -f, Sec. 4); any other
+ * kind is MT_ERR_INVALID_ARG.  Arguments, ownership and errors as mt_build.
+ */
+int mt_build_tree(const float *field, int64_t nx, int64_t ny, int64_t nz, int kind,
+                  uint32_t *triplets, void *workspace, size_t ws_bytes, void *stream);
 
 /*
  * mt_persistence_pairs -- zero-dimensional persistence pairs of a merge tree
@@ -147,6 +166,16 @@ int mt_batch_build(const float *fields, const int64_t *dims, int32_t n_fields,
                    uint32_t *triplets, uint32_t *birth, uint32_t *death,
                    float *birth_val, float *death_val, int64_t pair_capacity,
                    int64_t *pair_offsets, void *workspace, size_t ws_bytes, void *stream);
+
+/*
+ * mt_batch_build_tree -- mt_batch_build for either tree (kind as in
+ * mt_build_tree, the same for every field of the batch).  The kind is part of
+ * the cached graph's key.
+ */
+int mt_batch_build_tree(const float *fields, const int64_t *dims, int32_t n_fields, int kind,
+                        uint32_t *triplets, uint32_t *birth, uint32_t *death,
+                        float *birth_val, float *death_val, int64_t pair_capacity,
+                        int64_t *pair_offsets, void *workspace, size_t ws_bytes, void *stream);
 
 /*
  * mt_sync_status -- synchronize `stream` and return the status latched in

@@ -321,26 +321,28 @@ static int enqueue_setup(const Plan &p, const Ptrs &w, uint32_t clear_status, bo
 }
 
 template <class S>
-static int launch_local(const Plan &p, const ClassLaunch &cl, const Ptrs &w, const float *f, hipStream_t st)
+static int launch_local(const Plan &p, const ClassLaunch &cl, const Ptrs &w, const float *f, uint32_t flip,
+                        hipStream_t st)
 {
     MT_LAUNCH("k_local", HIP_KERNEL_NAME(k_local<S>), dim3((unsigned)cl.ntiles), dim3(S::NT), st, f, w.lbl, w.slot,
               w.mkey, (const FieldDesc *)w.D, (const int32_t *)w.tfield + cl.cb, (const int64_t *)w.tstart + cl.cb,
-              cl.nfc, cl.tile0, cl.ntiles, g_remap, (uint32_t)p.m_cap, g_cap, w.xface, w.h);
+              cl.nfc, cl.tile0, cl.ntiles, g_remap, (uint32_t)p.m_cap, g_cap, w.xface, flip, w.h);
     return MT_OK;
 }
 
 template <class S>
-static int launch_cross(const Plan &p, const ClassLaunch &cl, const Ptrs &w, const float *f, hipStream_t st)
+static int launch_cross(const Plan &p, const ClassLaunch &cl, const Ptrs &w, const float *f, uint32_t flip,
+                        hipStream_t st)
 {
     MT_LAUNCH("k_cross", HIP_KERNEL_NAME(k_cross<S>), dim3((unsigned)cl.ntiles), dim3(S::NT), st, f,
               (const uint32_t *)w.lbl, w.queue, (uint32_t)p.q_cap, (const FieldDesc *)w.D,
               (const int32_t *)w.tfield + cl.cb, (const int64_t *)w.tstart + cl.cb, cl.nfc, cl.tile0, cl.ntiles,
-              g_remap, w.qhist, (const uint64_t *)w.xface, w.h);
+              g_remap, w.qhist, (const uint64_t *)w.xface, flip, w.h);
     return MT_OK;
 }
 
 // The merge tree: triplets T (field-local ids) and, per chunk, pair counts.
-static int enqueue_build(const Plan &p, const Ptrs &w, const float *f, uint64_t *T, hipStream_t st)
+static int enqueue_build(const Plan &p, const Ptrs &w, const float *f, uint64_t *T, uint32_t flip, hipStream_t st)
 {
     const int nf = (int)p.d.size();
     const uint32_t n = (uint32_t)p.n_total;
@@ -350,14 +352,14 @@ static int enqueue_build(const Plan &p, const Ptrs &w, const float *f, uint64_t 
         const ClassLaunch &cl = p.cls[c];
         if (cl.ntiles == 0) continue;
         int rc = MT_OK;
-        with_shape(cl.shape, [&](auto s) { rc = launch_local<decltype(s)>(p, cl, w, f, st); });
+        with_shape(cl.shape, [&](auto s) { rc = launch_local<decltype(s)>(p, cl, w, f, flip, st); });
         if (rc != MT_OK) return rc;
     }
     for (int c = 0; c < 3; ++c) {
         const ClassLaunch &cl = p.cls[c];
         if (cl.ntiles == 0) continue;
         int rc = MT_OK;
-        with_shape(cl.shape, [&](auto s) { rc = launch_cross<decltype(s)>(p, cl, w, f, st); });
+        with_shape(cl.shape, [&](auto s) { rc = launch_cross<decltype(s)>(p, cl, w, f, flip, st); });
         if (rc != MT_OK) return rc;
     }
     // facts into ascending order of their saddle's key bin, per XCD queue
@@ -369,12 +371,12 @@ static int enqueue_build(const Plan &p, const Ptrs &w, const float *f, uint64_t 
     MT_LAUNCH("k_qscatter", k_qscatter, dim3(gq), dim3(kBlock), st, (const Fact *)w.queue, w.qbin,
               (uint32_t)p.q_cap, w.qhist, w.h);
     MT_LAUNCH("k_merge_q", k_merge_q, dim3(gq), dim3(kBlock), st, f, (const Fact *)w.qbin, (uint32_t)p.q_cap, w.slot,
-              (const uint64_t *)w.mkey, n, g_cap, w.h);
+              (const uint64_t *)w.mkey, n, g_cap, flip, w.h);
     const unsigned gm = (unsigned)std::min<int64_t>(8192, std::max<int64_t>(1, (p.m_cap + kBlock - 1) / kBlock));
-    MT_LAUNCH("k_repair_min", k_repair_min, dim3(gm), dim3(kBlock), st, f, w.slot, n, g_cap, w.h);
+    MT_LAUNCH("k_repair_min", k_repair_min, dim3(gm), dim3(kBlock), st, f, w.slot, n, g_cap, flip, w.h);
     MT_LAUNCH("k_repair_reg", k_repair_reg, dim3((unsigned)p.n_chunks), dim3(kBlock), st, f,
               (const uint32_t *)w.lbl, w.slot, (const uint64_t *)w.mkey, T, w.pcnt, (const FieldDesc *)w.D,
-              (const int64_t *)w.cs, nf, n, g_cap, w.h);
+              (const int64_t *)w.cs, nf, n, g_cap, flip, w.h);
     return MT_OK;
 }
 
@@ -486,9 +488,18 @@ size_t mt_batch_workspace_bytes(const int64_t *dims, int32_t n_fields)
     return p.lay.total;
 }
 
+static uint32_t kind_flip(int kind) { return kind == MT_TREE_SPLIT ? 0xffffffffu : 0u; }
+
 int mt_build(const float *field, int64_t nx, int64_t ny, int64_t nz, uint32_t *triplets, void *workspace,
              size_t ws_bytes, void *stream)
 {
+    return mt_build_tree(field, nx, ny, nz, MT_TREE_MERGE, triplets, workspace, ws_bytes, stream);
+}
+
+int mt_build_tree(const float *field, int64_t nx, int64_t ny, int64_t nz, int kind, uint32_t *triplets,
+                  void *workspace, size_t ws_bytes, void *stream)
+{
+    if (kind != MT_TREE_MERGE && kind != MT_TREE_SPLIT) return MT_ERR_INVALID_ARG;
     const int64_t dims[3] = {nx, ny, nz};
     Plan p;
     int rc = make_plan(dims, 1, p);
@@ -499,7 +510,7 @@ int mt_build(const float *field, int64_t nx, int64_t ny, int64_t nz, uint32_t *t
     const Ptrs w = ws_ptrs(p, workspace);
     rc = enqueue_setup(p, w, ~0u, true, st);
     if (rc != MT_OK) return rc;
-    return enqueue_build(p, w, field, (uint64_t *)triplets, st);
+    return enqueue_build(p, w, field, (uint64_t *)triplets, kind_flip(kind), st);
 }
 
 int mt_persistence_pairs(const float *field, const uint32_t *triplets, int64_t nx, int64_t ny, int64_t nz,
@@ -532,6 +543,16 @@ int mt_batch_build(const float *fields, const int64_t *dims, int32_t n_fields, u
                    uint32_t *death, float *birth_val, float *death_val, int64_t pair_capacity,
                    int64_t *pair_offsets, void *workspace, size_t ws_bytes, void *stream)
 {
+    return mt_batch_build_tree(fields, dims, n_fields, MT_TREE_MERGE, triplets, birth, death, birth_val, death_val,
+                               pair_capacity, pair_offsets, workspace, ws_bytes, stream);
+}
+
+int mt_batch_build_tree(const float *fields, const int64_t *dims, int32_t n_fields, int kind, uint32_t *triplets,
+                        uint32_t *birth, uint32_t *death, float *birth_val, float *death_val,
+                        int64_t pair_capacity, int64_t *pair_offsets, void *workspace, size_t ws_bytes,
+                        void *stream)
+{
+    if (kind != MT_TREE_MERGE && kind != MT_TREE_SPLIT) return MT_ERR_INVALID_ARG;
     Plan p;
     int rc = make_plan(dims, n_fields, p);
     if (rc != MT_OK) return rc;
@@ -545,10 +566,10 @@ int mt_batch_build(const float *fields, const int64_t *dims, int32_t n_fields, u
     std::string key;
     key.reserve(96 + 24 * n_fields);
     char buf[320];
-    snprintf(buf, sizeof buf, "%d|%p|%p|%p|%p|%p|%p|%lld|%p|%p|%zu|%d|%u|%d,%d,%d", dev, (const void *)fields,
-             (void *)triplets, (void *)birth, (void *)death, (void *)birth_val, (void *)death_val,
-             (long long)pair_capacity, (void *)pair_offsets, workspace, ws_bytes, g_remap, g_cap, p.cls[0].shape,
-             p.cls[1].shape, p.cls[2].shape);
+    snprintf(buf, sizeof buf, "%d|%d|%p|%p|%p|%p|%p|%p|%lld|%p|%p|%zu|%d|%u|%d,%d,%d", dev, kind,
+             (const void *)fields, (void *)triplets, (void *)birth, (void *)death, (void *)birth_val,
+             (void *)death_val, (long long)pair_capacity, (void *)pair_offsets, workspace, ws_bytes, g_remap, g_cap,
+             p.cls[0].shape, p.cls[1].shape, p.cls[2].shape);
     key += buf;
     for (const FieldDesc &d : p.d) {
         snprintf(buf, sizeof buf, "|%d,%d,%d", d.nx, d.ny, d.nz);
@@ -563,7 +584,7 @@ int mt_batch_build(const float *fields, const int64_t *dims, int32_t n_fields, u
         const Ptrs w = ws_ptrs(p, workspace);
         if (hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed) != hipSuccess) return MT_ERR_HIP;
         int rc1 = enqueue_setup(p, w, ~0u, true, cs);
-        if (rc1 == MT_OK) rc1 = enqueue_build(p, w, fields, (uint64_t *)triplets, cs);
+        if (rc1 == MT_OK) rc1 = enqueue_build(p, w, fields, (uint64_t *)triplets, kind_flip(kind), cs);
         if (rc1 == MT_OK)
             rc1 = enqueue_pairs(p, w, false, fields, (const uint64_t *)triplets, pair_capacity, birth, death,
                                 birth_val, death_val, pair_offsets, cs);
@@ -679,7 +700,7 @@ int mt_autotune(const float *fields, const int64_t *dims, int32_t n_fields, uint
             for (int r = -1; r < reps && rc == MT_OK; ++r) {  // r = -1: warm-up
                 if (r == 0 && hipEventRecord(e0, st) != hipSuccess) rc = MT_ERR_HIP;
                 if (rc == MT_OK) rc = enqueue_setup(p, w, ~0u, true, st);
-                if (rc == MT_OK) rc = enqueue_build(p, w, fields, out, st);
+                if (rc == MT_OK) rc = enqueue_build(p, w, fields, out, 0u, st);
             }
             if (rc != MT_OK) break;
             if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) { rc = MT_ERR_HIP; break; }

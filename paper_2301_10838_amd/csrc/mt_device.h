@@ -129,9 +129,12 @@ __device__ __forceinline__ uint32_t okey(float x)
     return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
 }
 
-__device__ __forceinline__ uint64_t vkey(const float *__restrict__ f, uint32_t id)
+// flip = 0: the order of the values (merge tree, sublevel sets); flip = ~0:
+// the reversed order (split tree, superlevel sets = the merge tree of -f),
+// ids still breaking ties upward.
+__device__ __forceinline__ uint64_t vkey(const float *__restrict__ f, uint32_t id, uint32_t flip)
 {
-    return ((uint64_t)okey(f[id]) << 32) | id;
+    return ((uint64_t)(okey(f[id]) ^ flip) << 32) | id;
 }
 
 __device__ __forceinline__ uint32_t lo32(uint64_t t) { return (uint32_t)t; }
@@ -167,10 +170,10 @@ __device__ __forceinline__ SlotRead ld_slot(Slot *__restrict__ S, uint32_t x)
 
 // Key of the saddle of a slot read: the cached key if it belongs to that
 // saddle, else the value read from the field.
-__device__ __forceinline__ uint64_t saddle_key(const SlotRead &r, const float *__restrict__ f)
+__device__ __forceinline__ uint64_t saddle_key(const SlotRead &r, const float *__restrict__ f, uint32_t flip)
 {
     const uint32_t s = lo32(r.w);
-    return lo32(r.k) == s ? r.k : vkey(f, s);
+    return lo32(r.k) == s ? r.k : vkey(f, s, flip);
 }
 
 template <typename I>
@@ -347,7 +350,8 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
                                                  const FieldDesc *__restrict__ D, const int32_t *__restrict__ tfield,
                                                  const int64_t *__restrict__ tstart, int nfc, int64_t tile0,
                                                  int64_t ntiles, int remap, uint32_t mcap, uint32_t cap,
-                                                 uint64_t *__restrict__ xface, Header *__restrict__ h)
+                                                 uint64_t *__restrict__ xface, uint32_t flip,
+                                                 Header *__restrict__ h)
 {
     constexpr int NT = S::NT, VOL = S::VOL, TX = S::TX, TY = S::TY;
     static_assert(S::TY * S::TZ <= kXFace, "x face record");
@@ -407,7 +411,7 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
             const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
             const bool ok = valid(lx, ly, lz);
             nan |= ok && (fv[k] != fv[k]);
-            hk[p] = ok ? okey(fv[k]) : 0xffffffffu;
+            hk[p] = ok ? okey(fv[k]) ^ flip : 0xffffffffu;  // outside the field: above every vertex
         }
         if (__ballot(nan) != 0ull && (threadIdx.x & 63) == 0) atomicOr(&h->status, ST_NAN);
     }
@@ -663,16 +667,16 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
 // 2. Merge (Alg. 3) across tiles, on the minimum slots
 
 __device__ void gmerge(Slot *__restrict__ S, const uint64_t *__restrict__ mkey, const float *__restrict__ f,
-                       uint32_t M, uint32_t n, uint32_t u, uint32_t s, uint64_t ks, uint32_t v, uint32_t cap,
-                       uint32_t &err)
+                       uint32_t flip, uint32_t M, uint32_t n, uint32_t u, uint32_t s, uint64_t ks, uint32_t v,
+                       uint32_t cap, uint32_t &err)
 {
     SlotRead tu = ld_slot(S, u);
     SlotRead tv = ld_slot(S, v);
     for (uint32_t step = 0; step < cap; ++step) {
         const uint32_t u1 = hi32(tu.w), su = lo32(tu.w), v1 = hi32(tv.w), sv = lo32(tv.w);
         if (u1 >= M || v1 >= M || su >= n || sv >= n) { err |= ST_CORRUPT; return; }
-        if (u1 != u && saddle_key(tu, f) < ks) { u = u1; tu = ld_slot(S, u); continue; }
-        if (v1 != v && saddle_key(tv, f) < ks) { v = v1; tv = ld_slot(S, v); continue; }
+        if (u1 != u && saddle_key(tu, f, flip) < ks) { u = u1; tu = ld_slot(S, u); continue; }
+        if (v1 != v && saddle_key(tv, f, flip) < ks) { v = v1; tv = ld_slot(S, v); continue; }
         if (u == v) return;
         if (mkey[v] < mkey[u]) {  // the upper minimum is re-pointed
             const uint32_t w = u; u = v; v = w;
@@ -683,7 +687,7 @@ __device__ void gmerge(Slot *__restrict__ S, const uint64_t *__restrict__ mkey, 
                                                  __HIP_MEMORY_SCOPE_AGENT)) {
             st_relaxed(&S[v].k, ks);
             if (hi32(tv.w) == v) return;  // v was a root
-            const uint64_t kv = saddle_key(tv, f);  // merge the displaced triplet again
+            const uint64_t kv = saddle_key(tv, f, flip);  // merge the displaced triplet again
             s = lo32(tv.w);
             ks = kv;
             v = hi32(tv.w);
@@ -747,7 +751,8 @@ __global__ __launch_bounds__(S::NT) void k_cross(const float *__restrict__ f, co
                                                  const FieldDesc *__restrict__ D, const int32_t *__restrict__ tfield,
                                                  const int64_t *__restrict__ tstart, int nfc, int64_t tile0,
                                                  int64_t ntiles, int remap, uint32_t *__restrict__ qhist,
-                                                 const uint64_t *__restrict__ xface, Header *__restrict__ h)
+                                                 const uint64_t *__restrict__ xface, uint32_t flip,
+                                                 Header *__restrict__ h)
 {
     constexpr int TX = S::TX, TY = S::TY, TZ = S::TZ, NT = S::NT;
     // faces that can have a neighbour: a 2-D shape has no z face, a 1-D one no y face
@@ -802,7 +807,7 @@ __global__ __launch_bounds__(S::NT) void k_cross(const float *__restrict__ f, co
             kb = (rb & 0xffffffff00000000ull) | b;
         } else {
             za = lbl[a]; zb = lbl[b];
-            ka = vkey(f, a); kb = vkey(f, b);
+            ka = vkey(f, a, flip); kb = vkey(f, b, flip);
         }
         if (za >= M || zb >= M) { err |= ST_CORRUPT; continue; }
         const uint64_t ks = kb < ka ? ka : kb;  // the upper end is the saddle
@@ -986,7 +991,7 @@ __global__ __launch_bounds__(kBlock) void k_qscatter(const Fact *__restrict__ qu
 __global__ __launch_bounds__(kBlock) void k_merge_q(const float *__restrict__ f, const Fact *__restrict__ queue,
                                                     uint32_t qsub, Slot *__restrict__ slot,
                                                     const uint64_t *__restrict__ mkey, uint32_t n, uint32_t cap,
-                                                    Header *__restrict__ h)
+                                                    uint32_t flip, Header *__restrict__ h)
 {
     const uint32_t M = h->n_minima;
     const uint32_t x = blockIdx.x % 8, per = gridDim.x / 8;
@@ -996,7 +1001,7 @@ __global__ __launch_bounds__(kBlock) void k_merge_q(const float *__restrict__ f,
     for (uint32_t i = (blockIdx.x / 8) * kBlock + threadIdx.x; i < Q; i += per * kBlock) {
         const Fact q = mq[i];
         if (q.a >= M || q.b >= M || lo32(q.ks) >= n) { err |= ST_CORRUPT; continue; }
-        gmerge(slot, mkey, f, M, n, q.a, lo32(q.ks), q.ks, q.b, cap, err);
+        gmerge(slot, mkey, f, flip, M, n, q.a, lo32(q.ks), q.ks, q.b, cap, err);
     }
     if (err) atomicOr(&h->status, err);
 }
@@ -1006,15 +1011,16 @@ __global__ __launch_bounds__(kBlock) void k_merge_q(const float *__restrict__ f,
 
 // Representative: follow the slots from x while the saddle is at or below
 // `level` and x is no root; the last minimum reached.
-__device__ __forceinline__ uint32_t chase(Slot *__restrict__ S, const float *__restrict__ f, uint32_t M, uint32_t n,
-                                          uint32_t x, uint64_t level, uint32_t cap, uint32_t &err)
+__device__ __forceinline__ uint32_t chase(Slot *__restrict__ S, const float *__restrict__ f, uint32_t flip,
+                                          uint32_t M, uint32_t n, uint32_t x, uint64_t level, uint32_t cap,
+                                          uint32_t &err)
 {
     for (uint32_t step = 0; step < cap; ++step) {
         const SlotRead t = ld_slot(S, x);
         const uint32_t v = hi32(t.w), s = lo32(t.w);
         if (v >= M || s >= n) { err |= ST_CORRUPT; return x; }
         if (v == x) return x;
-        if (saddle_key(t, f) > level) return x;
+        if (saddle_key(t, f, flip) > level) return x;
         x = v;
     }
     err |= ST_LIVELOCK;
@@ -1022,7 +1028,7 @@ __device__ __forceinline__ uint32_t chase(Slot *__restrict__ S, const float *__r
 }
 
 __global__ __launch_bounds__(kBlock) void k_repair_min(const float *__restrict__ f, Slot *__restrict__ S, uint32_t n,
-                                                       uint32_t cap, Header *__restrict__ h)
+                                                       uint32_t cap, uint32_t flip, Header *__restrict__ h)
 {
     const uint32_t M = h->n_minima;
     uint32_t err = 0;
@@ -1031,7 +1037,7 @@ __global__ __launch_bounds__(kBlock) void k_repair_min(const float *__restrict__
         const uint32_t v = hi32(t.w), s = lo32(t.w);
         if (v == m) continue;
         if (v >= M || s >= n) { err |= ST_CORRUPT; continue; }
-        const uint32_t r = chase(S, f, M, n, v, saddle_key(t, f), cap, err);
+        const uint32_t r = chase(S, f, flip, M, n, v, saddle_key(t, f, flip), cap, err);
         if (r != v) st_relaxed(&S[m].w, pack(s, r));
     }
     if (err) atomicOr(&h->status, err);
@@ -1048,7 +1054,8 @@ __global__ __launch_bounds__(kBlock) void k_repair_reg(const float *__restrict__
                                                        const Slot *__restrict__ S, const uint64_t *__restrict__ mkey,
                                                        uint64_t *__restrict__ T, uint32_t *__restrict__ pcnt,
                                                        const FieldDesc *__restrict__ D, const int64_t *__restrict__ cs,
-                                                       int nf, uint32_t n, uint32_t cap, Header *__restrict__ h)
+                                                       int nf, uint32_t n, uint32_t cap, uint32_t flip,
+                                                       Header *__restrict__ h)
 {
     __shared__ uint32_t sp[kBlock / 64], sr[kBlock / 64];
     const int64_t c = blockIdx.x;
@@ -1070,7 +1077,7 @@ __global__ __launch_bounds__(kBlock) void k_repair_reg(const float *__restrict__
             live |= (uint32_t)in << i;
             u[i] = off + (uint32_t)(in ? j : lo);
             z[i] = lbl[u[i]];
-            level[i] = vkey(f, u[i]);
+            level[i] = vkey(f, u[i], flip);
         }
 #pragma unroll
         for (int i = 0; i < RV; ++i) {
@@ -1094,7 +1101,7 @@ __global__ __launch_bounds__(kBlock) void k_repair_reg(const float *__restrict__
                 live &= ~(1u << i);
                 continue;
             }
-            const uint64_t sk = lo32(tk[i]) == s0 ? tk[i] : vkey(f, s0);
+            const uint64_t sk = lo32(tk[i]) == s0 ? tk[i] : vkey(f, s0, flip);
             if (lo32(mz[i]) == u[i]) {  // u is a local minimum: its own repaired triplet
                 s[i] = s0;
                 if ((live >> i) & 1u) {
@@ -1132,7 +1139,7 @@ __global__ __launch_bounds__(kBlock) void k_repair_reg(const float *__restrict__
                     live &= ~(1u << i);
                     continue;
                 }
-                const uint64_t sk = lo32(tk[i]) == sv ? tk[i] : vkey(f, sv);
+                const uint64_t sk = lo32(tk[i]) == sv ? tk[i] : vkey(f, sv, flip);
                 if (v == x[i] || sk > level[i]) act &= ~(1u << i);
                 else x[i] = v;
             }

@@ -31,8 +31,21 @@ EXPORTS = [
     "mt_batch_build", "mt_sync_status", "mt_build_stats", "mt_pairs_backward", "mt_release_caches",
     "mt_profile_begin",
     "mt_profile_end", "mt_profile_count", "mt_profile_get", "mt_tile_shape_count", "mt_tile_shape_info",
-    "mt_set_tile_shape", "mt_get_tile_shape", "mt_autotune_workspace_bytes", "mt_autotune",
+    "mt_set_tile_shape", "mt_get_tile_shape", "mt_autotune_workspace_bytes", "mt_autotune", "mt_build_tree",
+    "mt_batch_build_tree",
 ]
+
+# tree kinds (include/mt.h)
+MT_TREE_MERGE, MT_TREE_SPLIT = 0, 1
+_KINDS = {"merge": MT_TREE_MERGE, "split": MT_TREE_SPLIT}
+
+
+def _kind(kind) -> int:
+    if isinstance(kind, str):
+        if kind not in _KINDS:
+            raise ValueError(f"tree kind must be one of {sorted(_KINDS)}")
+        return _KINDS[kind]
+    return int(kind)
 
 
 class MTError(RuntimeError):
@@ -61,10 +74,14 @@ def load_library():
     lib.mt_batch_workspace_bytes.restype = SZ
     lib.mt_build.argtypes = [P, I64, I64, I64, P, P, SZ, P]
     lib.mt_build.restype = ctypes.c_int
+    lib.mt_build_tree.argtypes = [P, I64, I64, I64, ctypes.c_int, P, P, SZ, P]
+    lib.mt_build_tree.restype = ctypes.c_int
     lib.mt_persistence_pairs.argtypes = [P, P, I64, I64, I64, P, P, P, P, I64, P, P, P, SZ, P]
     lib.mt_persistence_pairs.restype = ctypes.c_int
     lib.mt_batch_build.argtypes = [P, P, I32, P, P, P, P, P, I64, P, P, SZ, P]
     lib.mt_batch_build.restype = ctypes.c_int
+    lib.mt_batch_build_tree.argtypes = [P, P, I32, ctypes.c_int, P, P, P, P, P, I64, P, P, SZ, P]
+    lib.mt_batch_build_tree.restype = ctypes.c_int
     lib.mt_sync_status.argtypes = [P, P, P, P]
     lib.mt_sync_status.restype = ctypes.c_int
     lib.mt_build_stats.argtypes = [P, P, P, P]
@@ -136,8 +153,10 @@ def alloc_workspace(nbytes: int, device) -> torch.Tensor:
 
 
 def mt_build(field: torch.Tensor, triplets: torch.Tensor | None = None,
-             workspace: torch.Tensor | None = None) -> torch.Tensor:
-    """Triplets T[u] = (s, v) of the merge tree of `field` (int32 [N, 2], uint32 bit patterns)."""
+             workspace: torch.Tensor | None = None, kind="merge") -> torch.Tensor:
+    """Triplets T[u] = (s, v) of the merge tree (kind "merge") or split tree
+    (kind "split": the merge tree of -f) of `field` (int32 [N, 2], uint32 bit
+    patterns)."""
     lib = load_library()
     f = _field(field)
     nx, ny, nz = grid_dims(f.shape)
@@ -146,9 +165,9 @@ def mt_build(field: torch.Tensor, triplets: torch.Tensor | None = None,
         triplets = torch.empty((N, 2), dtype=torch.int32, device=f.device)
     if workspace is None:
         workspace = alloc_workspace(lib.mt_workspace_bytes(nx, ny, nz), f.device)
-    rc = lib.mt_build(f.data_ptr(), nx, ny, nz, triplets.data_ptr(), workspace.data_ptr(),
-                      workspace.numel(), _stream_ptr(f.device))
-    _check(rc, "mt_build")
+    rc = lib.mt_build_tree(f.data_ptr(), nx, ny, nz, _kind(kind), triplets.data_ptr(), workspace.data_ptr(),
+                           workspace.numel(), _stream_ptr(f.device))
+    _check(rc, "mt_build_tree")
     return triplets
 
 
@@ -183,8 +202,9 @@ class BatchPlan:
     """Buffers of one batch configuration (reused across calls, so the library's
     cached graph for these pointers is replayed)."""
 
-    def __init__(self, shapes: Sequence[Sequence[int]], device, pair_capacity: int | None = None):
+    def __init__(self, shapes: Sequence[Sequence[int]], device, pair_capacity: int | None = None, kind="merge"):
         lib = load_library()
+        self.kind = _kind(kind)
         self.shapes = [tuple(int(s) for s in shp) for shp in shapes]
         self.dims = [grid_dims(s) for s in self.shapes]
         self.sizes = [nx * ny * nz for nx, ny, nz in self.dims]
@@ -218,12 +238,13 @@ class BatchPlan:
             self.fields[a:b].copy_(f.reshape(-1))
 
     def launch(self):
-        rc = load_library().mt_batch_build(
-            self.fields.data_ptr(), self._dims_c, len(self.dims), self.triplets.data_ptr(), self.birth.data_ptr(),
+        rc = load_library().mt_batch_build_tree(
+            self.fields.data_ptr(), self._dims_c, len(self.dims), self.kind, self.triplets.data_ptr(),
+            self.birth.data_ptr(),
             self.death.data_ptr(), self.bval.data_ptr(), self.dval.data_ptr(), self.pair_capacity,
             self.pair_offsets.data_ptr(), self.workspace.data_ptr(), self.workspace.numel(),
             _stream_ptr(self.device))
-        _check(rc, "mt_batch_build")
+        _check(rc, "mt_batch_build_tree")
 
     def sync_status(self):
         n_pairs = ctypes.c_int64(0)
@@ -240,10 +261,11 @@ class BatchPlan:
                                  self.death, grad_birth, grad_death, grad_field, accumulate)
 
 
-def mt_batch_build(fields: Sequence[torch.Tensor], plan: BatchPlan | None = None, sync: bool = True):
-    """Merge trees + pairs of many fields in one graph launch; returns the plan holding the outputs."""
+def mt_batch_build(fields: Sequence[torch.Tensor], plan: BatchPlan | None = None, sync: bool = True,
+                   kind="merge"):
+    """Merge (or split) trees + pairs of many fields in one graph launch; returns the plan holding the outputs."""
     if plan is None:
-        plan = BatchPlan([f.shape for f in fields], fields[0].device)
+        plan = BatchPlan([f.shape for f in fields], fields[0].device, kind=kind)
     plan.load(fields)
     plan.launch()
     if sync:

@@ -80,6 +80,13 @@ def test_host_argument_checks(lib):
     assert lib.mt_batch_build(fake, dims, 0, fake, fake, fake, fake, fake, 10, fake, fake, 1 << 20, None) == -1
     big = (ctypes.c_int64 * 6)(1 << 15, 1 << 15, 1, 1 << 15, 1 << 15, 1)
     assert lib.mt_batch_build(fake, big, 2, fake, fake, fake, fake, fake, 10, fake, fake, 1 << 20, None) == -2
+    # tree kind: only merge (0) and split (1)
+    good = (ctypes.c_int64 * 3)(8, 8, 8)
+    assert lib.mt_build_tree(fake, 8, 8, 8, 2, fake, fake, ws, None) == -1
+    assert lib.mt_build_tree(fake, 8, 8, 8, -1, fake, fake, ws, None) == -1
+    assert lib.mt_build_tree(fake, 0, 8, 8, 1, fake, fake, ws, None) == -1
+    assert lib.mt_batch_build_tree(fake, good, 1, 7, fake, fake, fake, fake, fake, 10, fake, fake, 1 << 20,
+                                   None) == -1
     # backward
     assert lib.mt_pairs_backward(dims, 1, fake, 0, None, None, None, None, fake, 0, None) == -1
     assert lib.mt_sync_status(None, None, None, None) == -6
