@@ -240,6 +240,43 @@ def bench_batch(dev, mt, lib, reps: int = 5):
     }
 
 
+def bench_split(ft, lib, mt, s, steps: int = 5):
+    """The split tree (merge tree of -f) of the timed field, build + pairs, and
+    its bit-identity with the merge tree of the negated field."""
+    import torch
+
+    nx, ny, nz = s.dims
+
+    def step():
+        rc = lib.mt_build_tree(ft.data_ptr(), nx, ny, nz, mt.MT_TREE_SPLIT, s.T.data_ptr(), s.ws.data_ptr(),
+                               s.ws.numel(), s.stream)
+        if rc != 0:
+            raise mt.MTError(rc, "mt_build_tree")
+        rc = lib.mt_persistence_pairs(ft.data_ptr(), s.T.data_ptr(), nx, ny, nz, s.b.data_ptr(), s.d.data_ptr(),
+                                      s.bv.data_ptr(), s.dv.data_ptr(), s.cap, ctypes.byref(s.np),
+                                      ctypes.byref(s.nr), s.ws.data_ptr(), s.ws.numel(), s.stream)
+        if rc != 0:
+            raise mt.MTError(rc, "mt_persistence_pairs")
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    T_split = s.T.clone()
+    neg = (-ft).contiguous()
+    rc = lib.mt_build(neg.data_ptr(), nx, ny, nz, s.T.data_ptr(), s.ws.data_ptr(), s.ws.numel(), s.stream)
+    if rc != 0:
+        raise mt.MTError(rc, "mt_build")
+    torch.cuda.synchronize()
+    same = bool(torch.equal(T_split, s.T))
+    del neg, T_split
+    return {"workload": "grf512 split tree", "ms_per_step": dt * 1e3, "Mvertices_per_s": s.N / dt / 1e6,
+            "pairs": s.np.value, "equals_merge_tree_of_negated_field": same}
+
+
 def bench_backward(dev, mt, steps: int = 20):
     import torch
 
@@ -446,7 +483,8 @@ def main():
         out["copy_calibration_bytes"] = {"read": src.numel() * 4, "write": dst.numel() * 4}
         del src, dst
     if not args.no_secondary:
-        out["secondary"] = {"batched": bench_batch(dev, mt, lib), "backward": bench_backward(dev, mt)}
+        out["secondary"] = {"batched": bench_batch(dev, mt, lib), "backward": bench_backward(dev, mt),
+                            "split_tree": bench_split(ft, lib, mt, s)}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(f, dev, mt, lib)
     print(json.dumps(out), flush=True)
