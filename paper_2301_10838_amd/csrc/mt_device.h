@@ -1260,48 +1260,58 @@ __global__ __launch_bounds__(1024) void k_pairs_scan(uint32_t *__restrict__ cnt,
 }
 
 // Ordered compaction: ascending vertex id within the chunk, chunks in order.
+// Wave w owns the w-th quarter of the chunk: all of a lane's triplets are
+// read first (their loads in flight together), one barrier shares the wave
+// counts, and each wave then writes its pairs in order with ballots alone.
 __global__ __launch_bounds__(kBlock) void k_pairs_write(const float *__restrict__ f, const uint64_t *__restrict__ T,
                                                         const FieldDesc *__restrict__ D, const int64_t *__restrict__ cs,
                                                         int nf, const uint32_t *__restrict__ base, int64_t capacity,
                                                         uint32_t *__restrict__ birth, uint32_t *__restrict__ death,
                                                         float *__restrict__ bval, float *__restrict__ dval)
 {
+    constexpr int R = kChunk / kBlock;
+    constexpr int WSPAN = kChunk / (kBlock / 64);  // vertices per wave
+    static_assert(R <= 32, "pair bits of a lane fit one word");
     __shared__ uint32_t wsum[kBlock / 64];
     const int64_t c = blockIdx.x;
     const FieldDesc d = D[search(cs, nf, c)];
     const int64_t lo = (c - d.chunk_start) * kChunk;
     const int64_t hi = min(lo + (int64_t)kChunk, d.n);
     const uint32_t off = (uint32_t)d.offset;
-    const int wave = threadIdx.x >> 6;
-    int64_t run = base[c];
-    for (int64_t r0 = lo; r0 < hi; r0 += kBlock) {
-        const int64_t j = r0 + threadIdx.x;
-        bool p = false;
-        uint32_t s_loc = 0;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    uint32_t sl[R], pm = 0, np = 0, err = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t j = lo + wave * WSPAN + r * 64 + lane;
+        sl[r] = 0;
         if (j < hi) {
             bool root;
-            uint32_t err = 0;
-            p = classify(T, off, (uint32_t)d.n, j, s_loc, root, err);
-        }
-        const uint64_t m = __ballot(p);
-        if ((threadIdx.x & 63) == 0) wsum[wave] = (uint32_t)__popcll(m);
-        __syncthreads();
-        uint32_t wb = 0, tot = 0;
-        for (int w = 0; w < kBlock / 64; ++w) {
-            wb += (w < wave) ? wsum[w] : 0u;
-            tot += wsum[w];
-        }
-        if (p) {
-            const int64_t pos = run + wb + (uint32_t)__popcll(m & lanemask_lt());
-            if (pos < capacity) {
-                birth[pos] = (uint32_t)j;
-                death[pos] = s_loc;
-                bval[pos] = f[off + (uint32_t)j];
-                dval[pos] = f[off + s_loc];
+            if (classify(T, off, (uint32_t)d.n, j, sl[r], root, err)) {
+                pm |= 1u << r;
+                ++np;
             }
         }
-        run += tot;
-        __syncthreads();
+    }
+    for (int o = 32; o > 0; o >>= 1) np += __shfl_xor(np, o);
+    if (lane == 0) wsum[wave] = np;
+    __syncthreads();
+    int64_t run = base[c];
+    for (int w = 0; w < wave; ++w) run += wsum[w];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const bool p = (pm >> r) & 1u;
+        const uint64_t m = __ballot(p);
+        if (p) {
+            const int64_t pos = run + (uint32_t)__popcll(m & lanemask_lt());
+            const uint32_t j = (uint32_t)(lo + wave * WSPAN + r * 64 + lane);
+            if (pos < capacity) {
+                birth[pos] = j;
+                death[pos] = sl[r];
+                bval[pos] = f[off + j];
+                dval[pos] = f[off + sl[r]];
+            }
+        }
+        run += (uint32_t)__popcll(m);
     }
 }
 
