@@ -158,6 +158,16 @@ def test_grf512_properties(dev):
     assert np.array_equal(T2, T)
 
 
+def test_grf512_exact(dev):
+    """Full-size 512^3 log-normal field, the benchmark's own configuration:
+    every triplet and every pair against the oracle (about 40 s of one core)."""
+    f = fields.workload("grf512")[0]
+    print("case grf512 exact: gpu", flush=True)
+    T, prs = gpu_tree(f, dev)
+    print("case grf512 exact: oracle", flush=True)
+    assert_matches_oracle(f, T, prs, "grf512")
+
+
 def test_nan_reported(dev):
     import paper_2301_10838_amd.mt as mt
 
