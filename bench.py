@@ -44,7 +44,7 @@ ALGO_BYTES_PER_VERTEX = {
     "k_repair_min": 0,   # per-minimum term below
     "k_repair_reg": 16,  # read label and f, write the triplet
     "k_pairs_count": 8,  # read the triplet
-    "k_pairs_write": 8,  # read the triplet (+16 per pair written)
+    "k_pairs_write": 8,  # read the triplet (+24 per pair: both values read, the pair written)
 }
 
 
@@ -62,7 +62,7 @@ def algo_bytes(kernel: str, n_vertices: int, n_pairs: int, n_local_minima: int, 
     if kernel == "k_repair_min":
         b += 16 * n_local_minima   # read (and rewrite) every slot once
     if kernel == "k_pairs_write":
-        b += 16 * n_pairs          # birth, death ids and values
+        b += 24 * n_pairs          # f at birth and death read; birth, death ids and values written
     return float(b)
 
 
@@ -125,18 +125,15 @@ class Single:
         self.nr = ctypes.c_int64(0)
         self.stream = torch.cuda.current_stream(dev).cuda_stream
 
-    def step(self):
+    def step(self, kind=0):
+        """Tree and pairs in one call (mt_build_pairs); kind 0 merge, 1 split."""
         nx, ny, nz = self.dims
-        rc = self.lib.mt_build(self.ft.data_ptr(), nx, ny, nz, self.T.data_ptr(), self.ws.data_ptr(),
-                               self.ws.numel(), self.stream)
+        rc = self.lib.mt_build_pairs(self.ft.data_ptr(), nx, ny, nz, kind, self.T.data_ptr(), self.b.data_ptr(),
+                                     self.d.data_ptr(), self.bv.data_ptr(), self.dv.data_ptr(), self.cap,
+                                     ctypes.byref(self.np), ctypes.byref(self.nr), self.ws.data_ptr(),
+                                     self.ws.numel(), self.stream)
         if rc != 0:
-            raise self.mt.MTError(rc, "mt_build")
-        rc = self.lib.mt_persistence_pairs(self.ft.data_ptr(), self.T.data_ptr(), nx, ny, nz, self.b.data_ptr(),
-                                           self.d.data_ptr(), self.bv.data_ptr(), self.dv.data_ptr(), self.cap,
-                                           ctypes.byref(self.np), ctypes.byref(self.nr), self.ws.data_ptr(),
-                                           self.ws.numel(), self.stream)
-        if rc != 0:
-            raise self.mt.MTError(rc, "mt_persistence_pairs")
+            raise self.mt.MTError(rc, "mt_build_pairs")
         return self.np.value, self.nr.value
 
     def build_stats(self):
@@ -201,7 +198,7 @@ def bench_batch(dev, mt, lib, reps: int = 5):
         plan.launch()
         P = plan.sync_status()
         tb.append(time.perf_counter() - t0)
-    # plain: one mt_build + mt_persistence_pairs per field
+    # plain: one mt_build_pairs call per field
     singles = [Single(plan.fields[plan.vertex_offsets[i]:plan.vertex_offsets[i + 1]].view(shapes[i]), lib, mt)
                for i in range(len(shapes))]
     for s in singles:
@@ -248,15 +245,7 @@ def bench_split(ft, lib, mt, s, steps: int = 5):
     nx, ny, nz = s.dims
 
     def step():
-        rc = lib.mt_build_tree(ft.data_ptr(), nx, ny, nz, mt.MT_TREE_SPLIT, s.T.data_ptr(), s.ws.data_ptr(),
-                               s.ws.numel(), s.stream)
-        if rc != 0:
-            raise mt.MTError(rc, "mt_build_tree")
-        rc = lib.mt_persistence_pairs(ft.data_ptr(), s.T.data_ptr(), nx, ny, nz, s.b.data_ptr(), s.d.data_ptr(),
-                                      s.bv.data_ptr(), s.dv.data_ptr(), s.cap, ctypes.byref(s.np),
-                                      ctypes.byref(s.nr), s.ws.data_ptr(), s.ws.numel(), s.stream)
-        if rc != 0:
-            raise mt.MTError(rc, "mt_persistence_pairs")
+        s.step(mt.MT_TREE_SPLIT)
 
     step()
     torch.cuda.synchronize()

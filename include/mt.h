@@ -142,6 +142,25 @@ int mt_persistence_pairs(const float *field, const uint32_t *triplets,
                          void *workspace, size_t ws_bytes, void *stream);
 
 /*
+ * mt_build_pairs -- mt_build_tree followed by mt_persistence_pairs in one
+ * call (Alg. 1, then the pairs of Sec. 1), with the same results.  The
+ * build's output pass already counts the pairs of every chunk of vertices,
+ * so the readout skips its own counting pass over T.
+ *
+ * kind: as in mt_build_tree.  field, triplets: as in mt_build.  birth,
+ * death, birth_val, death_val, capacity, n_pairs, n_roots: as in
+ * mt_persistence_pairs.  workspace: mt_workspace_bytes(nx, ny, nz) bytes.
+ * Errors: the synchronous ones of both calls; the status latched by the
+ * build or the readout (MT_ERR_NAN, MT_ERR_LIVELOCK, MT_ERR_CAPACITY) is
+ * returned.  Synchronizes `stream` once, at the end.
+ */
+int mt_build_pairs(const float *field, int64_t nx, int64_t ny, int64_t nz, int kind,
+                   uint32_t *triplets, uint32_t *birth, uint32_t *death,
+                   float *birth_val, float *death_val, int64_t capacity,
+                   int64_t *n_pairs, int64_t *n_roots,
+                   void *workspace, size_t ws_bytes, void *stream);
+
+/*
  * mt_batch_build -- merge trees and pairs of many fields of uneven sizes in
  * one graph launch.  This batching is not in the paper; each field gets
  * exactly the triplets and pairs that mt_build + mt_persistence_pairs give it.

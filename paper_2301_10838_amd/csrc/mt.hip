@@ -380,13 +380,14 @@ static int enqueue_build(const Plan &p, const Ptrs &w, const float *f, uint64_t 
     return MT_OK;
 }
 
-// Pairs of T: counts (unless the build already counted them), scan, ordered write.
-static int enqueue_pairs(const Plan &p, const Ptrs &w, bool count, const float *f, const uint64_t *T,
+// Pairs of T: counts (unless the build just counted them: its output pass
+// leaves the pair count of every chunk in the workspace), scan, ordered write.
+static int enqueue_pairs(const Plan &p, const Ptrs &w, bool after_build, const float *f, const uint64_t *T,
                          int64_t capacity, uint32_t *birth, uint32_t *death, float *bval, float *dval,
                          int64_t *pair_offsets, hipStream_t st)
 {
     const int nf = (int)p.d.size();
-    if (count)
+    if (!after_build)
         MT_LAUNCH("k_pairs_count", k_pairs_count, dim3((unsigned)p.n_chunks), dim3(kBlock), st, T,
                   (const FieldDesc *)w.D, (const int64_t *)w.cs, nf, w.pcnt, w.h);
     MT_LAUNCH("k_pairs_scan", k_pairs_scan, dim3(1), dim3(1024), st, w.pcnt, p.n_chunks, (const FieldDesc *)w.D, nf,
@@ -528,12 +529,38 @@ int mt_persistence_pairs(const float *field, const uint32_t *triplets, int64_t n
     const Ptrs w = ws_ptrs(p, workspace);
     rc = enqueue_setup(p, w, ST_CAPACITY | ST_CORRUPT, true, st);
     if (rc != MT_OK) return rc;
-    rc = enqueue_pairs(p, w, true, field, (const uint64_t *)triplets, capacity, birth, death, birth_val, death_val,
+    rc = enqueue_pairs(p, w, false, field, (const uint64_t *)triplets, capacity, birth, death, birth_val, death_val,
                        nullptr, st);
     if (rc != MT_OK) return rc;
     Header h;
     rc = read_header(workspace, st, h);
     if (rc != MT_OK) return rc;
+    *n_pairs = h.total_pairs;
+    if (n_roots) *n_roots = h.roots;
+    return status_to_code(h.status);
+}
+
+int mt_build_pairs(const float *field, int64_t nx, int64_t ny, int64_t nz, int kind, uint32_t *triplets,
+                   uint32_t *birth, uint32_t *death, float *birth_val, float *death_val, int64_t capacity,
+                   int64_t *n_pairs, int64_t *n_roots, void *workspace, size_t ws_bytes, void *stream)
+{
+    if (kind != MT_TREE_MERGE && kind != MT_TREE_SPLIT) return MT_ERR_INVALID_ARG;
+    const int64_t dims[3] = {nx, ny, nz};
+    Plan p;
+    int rc = make_plan(dims, 1, p);
+    if (rc != MT_OK) return rc;
+    if (!field || !triplets || ((uintptr_t)triplets & 7u) || !n_pairs || capacity < 0) return MT_ERR_INVALID_ARG;
+    if (capacity > 0 && (!birth || !death || !birth_val || !death_val)) return MT_ERR_INVALID_ARG;
+    if ((rc = check_ws(p, workspace, ws_bytes)) != MT_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const Ptrs w = ws_ptrs(p, workspace);
+    if ((rc = enqueue_setup(p, w, ~0u, true, st)) != MT_OK) return rc;
+    if ((rc = enqueue_build(p, w, field, (uint64_t *)triplets, kind_flip(kind), st)) != MT_OK) return rc;
+    rc = enqueue_pairs(p, w, true, field, (const uint64_t *)triplets, capacity, birth, death, birth_val, death_val,
+                       nullptr, st);
+    if (rc != MT_OK) return rc;
+    Header h;
+    if ((rc = read_header(workspace, st, h)) != MT_OK) return rc;
     *n_pairs = h.total_pairs;
     if (n_roots) *n_roots = h.roots;
     return status_to_code(h.status);
@@ -586,7 +613,7 @@ int mt_batch_build_tree(const float *fields, const int64_t *dims, int32_t n_fiel
         int rc1 = enqueue_setup(p, w, ~0u, true, cs);
         if (rc1 == MT_OK) rc1 = enqueue_build(p, w, fields, (uint64_t *)triplets, kind_flip(kind), cs);
         if (rc1 == MT_OK)
-            rc1 = enqueue_pairs(p, w, false, fields, (const uint64_t *)triplets, pair_capacity, birth, death,
+            rc1 = enqueue_pairs(p, w, true, fields, (const uint64_t *)triplets, pair_capacity, birth, death,
                                 birth_val, death_val, pair_offsets, cs);
         GraphEntry e;
         const hipError_t ec = hipStreamEndCapture(cs, &e.graph);

@@ -535,21 +535,23 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
     // is every edge of a tile with more minima than a tag can number.
     uint32_t err = 0;
     const bool tabled = (uint32_t)HALF <= ZMAX || cnt <= ZMAX;
-    auto insert = [&](uint64_t val, uint32_t za, uint32_t zb) {
-        const uint32_t tag = (uint32_t)(val & TAGM);
-        uint32_t si = (tag * 0x9E3779B1u) >> (32 - PB);
+    // One atomic min per probe: an empty entry is claimed; an entry of the
+    // same pair keeps the lower edge; an entry of another pair keeps the
+    // lower of the two words and the lane carries the other one on.  Entries
+    // move but are never dropped, so every pair's lowest edge ends in the
+    // table (or is merged directly); a pair left with a second, higher entry
+    // only costs a merge that changes nothing.
+    auto insert = [&](uint64_t val) {
+        uint32_t si = ((uint32_t)(val & TAGM) * 0x9E3779B1u) >> (32 - PB);
         for (int probe = 0; probe < 32; ++probe) {
-            uint64_t prev = ~0ull;
-            __hip_atomic_compare_exchange_strong(htab + si, &prev, val, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_WORKGROUP);
-            if (prev == ~0ull) return;
-            if ((prev & TAGM) == tag) {
-                if (val < prev) atomicMin((unsigned long long *)(htab + si), (unsigned long long)val);
-                return;
-            }
+            const uint64_t prev = __hip_atomic_fetch_min(htab + si, val, __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (prev == ~0ull || ((prev ^ val) & TAGM) == 0) return;
+            val = prev < val ? val : prev;
             si = (si + 1) & (H - 1);
         }
-        lds_merge<VOL>(TL, hk, mh, za, val >> (2 * ZB), zb, cnt, cap, err);
+        const uint32_t tag = (uint32_t)(val & TAGM);
+        lds_merge<VOL>(TL, hk, mh, tag & (ZMAX - 1), val >> (2 * ZB), tag >> ZB, cnt, cap, err);
     };
     // A lane first marks which of its (vertex, direction) slots hold such an
     // edge, then inserts one marked slot per round: a wave runs as many rounds
@@ -576,7 +578,7 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
         const uint64_t ka = lkey<PB>(hk, p), kb = lkey<PB>(hk, q);
         const uint64_t ks = kb < ka ? ka : kb;  // the upper end is the saddle
         if (tabled)
-            insert((ks << (2 * ZB)) | min(za, zb) | ((uint64_t)max(za, zb) << ZB), za, zb);
+            insert((ks << (2 * ZB)) | min(za, zb) | ((uint64_t)max(za, zb) << ZB));
         else
             lds_merge<VOL>(TL, hk, mh, za, ks, zb, cnt, cap, err);
     }
@@ -1259,59 +1261,96 @@ __global__ __launch_bounds__(1024) void k_pairs_scan(uint32_t *__restrict__ cnt,
     }
 }
 
+// Position of the k-th set bit (k < popcount) of a 64-bit word, by halving.
+__device__ __forceinline__ uint32_t select_bit(uint64_t m, uint32_t k)
+{
+    uint32_t pos = 0;
+#pragma unroll
+    for (int w = 32; w >= 1; w >>= 1) {
+        const uint32_t c = (uint32_t)__popcll(m & ((1ull << w) - 1));
+        if (k >= c) { k -= c; pos += w; m >>= w; }
+    }
+    return pos;
+}
+
 // Ordered compaction: ascending vertex id within the chunk, chunks in order.
-// Wave w owns the w-th quarter of the chunk: all of a lane's triplets are
-// read first (their loads in flight together), one barrier shares the wave
-// counts, and each wave then writes its pairs in order with ballots alone.
+// Wave w owns the w-th quarter of the chunk.  It reads its triplets (all
+// loads in flight, coalesced), keeps one ballot word of pair births per 64
+// vertices (word r in lane r) and parks the death ids in LDS; one barrier
+// shares the wave totals.  Then lane k of a pass takes the wave's k-th pair
+// (its word by the word counts' prefix, its bit by halving), so the value
+// gathers and the stores run on dense lanes, 64 consecutive pairs a pass.
 __global__ __launch_bounds__(kBlock) void k_pairs_write(const float *__restrict__ f, const uint64_t *__restrict__ T,
                                                         const FieldDesc *__restrict__ D, const int64_t *__restrict__ cs,
                                                         int nf, const uint32_t *__restrict__ base, int64_t capacity,
                                                         uint32_t *__restrict__ birth, uint32_t *__restrict__ death,
                                                         float *__restrict__ bval, float *__restrict__ dval)
 {
-    constexpr int R = kChunk / kBlock;
     constexpr int WSPAN = kChunk / (kBlock / 64);  // vertices per wave
-    static_assert(R <= 32, "pair bits of a lane fit one word");
+    constexpr int NWD = WSPAN / 64;                // ballot words per wave
+    static_assert(NWD <= 64 && (NWD & (NWD - 1)) == 0, "one word per lane");
+    __shared__ uint32_t sdeath[kChunk];
     __shared__ uint32_t wsum[kBlock / 64];
     const int64_t c = blockIdx.x;
     const FieldDesc d = D[search(cs, nf, c)];
     const int64_t lo = (c - d.chunk_start) * kChunk;
     const int64_t hi = min(lo + (int64_t)kChunk, d.n);
-    const uint32_t off = (uint32_t)d.offset;
+    const uint32_t off = (uint32_t)d.offset, nloc = (uint32_t)d.n;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    uint32_t sl[R], pm = 0, np = 0, err = 0;
+    const int64_t w0 = lo + (int64_t)wave * WSPAN;
+    uint32_t sl[NWD], err = 0;
+    bool pf[NWD];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int64_t j = lo + wave * WSPAN + r * 64 + lane;
+    for (int r = 0; r < NWD; ++r) {
+        const int64_t j = w0 + r * 64 + lane;
+        pf[r] = false;
         sl[r] = 0;
         if (j < hi) {
             bool root;
-            if (classify(T, off, (uint32_t)d.n, j, sl[r], root, err)) {
-                pm |= 1u << r;
-                ++np;
-            }
+            pf[r] = classify(T, off, nloc, j, sl[r], root, err);
         }
     }
-    for (int o = 32; o > 0; o >>= 1) np += __shfl_xor(np, o);
-    if (lane == 0) wsum[wave] = np;
+    uint64_t wd = 0;  // lane r < NWD: the ballot word of vertices w0 + 64 r + [0, 64)
+#pragma unroll
+    for (int r = 0; r < NWD; ++r) {
+        const uint64_t m = __ballot(pf[r]);
+        if (lane == r) wd = m;
+        if (pf[r]) sdeath[wave * WSPAN + r * 64 + lane] = sl[r];
+    }
+    const uint32_t cnt = (uint32_t)__popcll(wd);
+    uint32_t inc = cnt;  // inclusive prefix of the word counts over lanes < NWD
+#pragma unroll
+    for (int o = 1; o < NWD; o <<= 1) {
+        const uint32_t t = __shfl_up(inc, o);
+        if (lane >= o) inc += t;
+    }
+    const uint32_t total = __shfl(inc, NWD - 1);
+    if (lane == 0) wsum[wave] = total;
     __syncthreads();
     int64_t run = base[c];
     for (int w = 0; w < wave; ++w) run += wsum[w];
+    for (uint32_t k0 = 0; k0 < total; k0 += 64) {
+        const uint32_t k = k0 + lane;
+        // the word holding pair k: the first word whose inclusive prefix exceeds k
+        uint32_t w = 0;
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const bool p = (pm >> r) & 1u;
-        const uint64_t m = __ballot(p);
-        if (p) {
-            const int64_t pos = run + (uint32_t)__popcll(m & lanemask_lt());
-            const uint32_t j = (uint32_t)(lo + wave * WSPAN + r * 64 + lane);
-            if (pos < capacity) {
-                birth[pos] = j;
-                death[pos] = sl[r];
-                bval[pos] = f[off + j];
-                dval[pos] = f[off + sl[r]];
-            }
+        for (int st = NWD / 2; st >= 1; st >>= 1) {
+            const uint32_t pre = __shfl(inc, (int)(w + st - 1));
+            if (pre <= k) w += st;
         }
-        run += (uint32_t)__popcll(m);
+        const uint32_t before = __shfl(inc, (int)w) - __shfl(cnt, (int)w);
+        const uint64_t m = __shfl(wd, (int)w);
+        if (k >= total) continue;
+        const uint32_t q = w * 64 + select_bit(m, k - before);  // position in the wave's quarter
+        const uint32_t j = (uint32_t)w0 + q;
+        const uint32_t sv = sdeath[wave * WSPAN + q];
+        const int64_t pos = run + k;
+        if (pos < capacity) {
+            birth[pos] = j;
+            death[pos] = sv;
+            bval[pos] = f[off + j];
+            dval[pos] = f[off + sv];
+        }
     }
 }
 

@@ -7,7 +7,7 @@ It never falls back to another implementation: without the built library, or
 without a GPU, every call raises.
 
 Functions keep the C names: ``mt_build``, ``mt_persistence_pairs``,
-``mt_batch_build``, ``mt_pairs_backward``; ``MergeTreePairs`` wraps the batch
+``mt_build_pairs``, ``mt_batch_build``, ``mt_pairs_backward``; ``MergeTreePairs`` wraps the batch
 build and the backward scatter as a ``torch.autograd.Function``.
 """
 from __future__ import annotations
@@ -32,7 +32,7 @@ EXPORTS = [
     "mt_profile_begin",
     "mt_profile_end", "mt_profile_count", "mt_profile_get", "mt_tile_shape_count", "mt_tile_shape_info",
     "mt_set_tile_shape", "mt_get_tile_shape", "mt_autotune_workspace_bytes", "mt_autotune", "mt_build_tree",
-    "mt_batch_build_tree",
+    "mt_batch_build_tree", "mt_build_pairs",
 ]
 
 # tree kinds (include/mt.h)
@@ -78,6 +78,8 @@ def load_library():
     lib.mt_build_tree.restype = ctypes.c_int
     lib.mt_persistence_pairs.argtypes = [P, P, I64, I64, I64, P, P, P, P, I64, P, P, P, SZ, P]
     lib.mt_persistence_pairs.restype = ctypes.c_int
+    lib.mt_build_pairs.argtypes = [P, I64, I64, I64, ctypes.c_int, P, P, P, P, P, I64, P, P, P, SZ, P]
+    lib.mt_build_pairs.restype = ctypes.c_int
     lib.mt_batch_build.argtypes = [P, P, I32, P, P, P, P, P, I64, P, P, SZ, P]
     lib.mt_batch_build.restype = ctypes.c_int
     lib.mt_batch_build_tree.argtypes = [P, P, I32, ctypes.c_int, P, P, P, P, P, I64, P, P, SZ, P]
@@ -196,6 +198,35 @@ def mt_persistence_pairs(field: torch.Tensor, triplets: torch.Tensor, capacity: 
     _check(rc, "mt_persistence_pairs")
     P = n_pairs.value
     return birth[:P], death[:P], bval[:P], dval[:P], n_roots.value
+
+
+def mt_build_pairs(field: torch.Tensor, kind="merge", capacity: int | None = None,
+                   triplets: torch.Tensor | None = None, workspace: torch.Tensor | None = None):
+    """Tree and pairs in one call: (triplets, birth, death, birth_val,
+    death_val, n_roots), the results of mt_build then mt_persistence_pairs."""
+    lib = load_library()
+    f = _field(field)
+    nx, ny, nz = grid_dims(f.shape)
+    N = nx * ny * nz
+    if capacity is None:
+        capacity = N // 2 + 1
+    dev = f.device
+    if triplets is None:
+        triplets = torch.empty((N, 2), dtype=torch.int32, device=dev)
+    birth = torch.empty(max(capacity, 1), dtype=torch.int32, device=dev)
+    death = torch.empty_like(birth)
+    bval = torch.empty(max(capacity, 1), dtype=torch.float32, device=dev)
+    dval = torch.empty_like(bval)
+    if workspace is None:
+        workspace = alloc_workspace(lib.mt_workspace_bytes(nx, ny, nz), dev)
+    n_pairs = ctypes.c_int64(0)
+    n_roots = ctypes.c_int64(0)
+    rc = lib.mt_build_pairs(f.data_ptr(), nx, ny, nz, _kind(kind), triplets.data_ptr(), birth.data_ptr(),
+                            death.data_ptr(), bval.data_ptr(), dval.data_ptr(), capacity, ctypes.byref(n_pairs),
+                            ctypes.byref(n_roots), workspace.data_ptr(), workspace.numel(), _stream_ptr(dev))
+    _check(rc, "mt_build_pairs")
+    P = n_pairs.value
+    return triplets, birth[:P], death[:P], bval[:P], dval[:P], n_roots.value
 
 
 class BatchPlan:

@@ -74,6 +74,16 @@ def test_host_argument_checks(lib):
                                     None) == -1
     assert lib.mt_persistence_pairs(fake, fake, 8, 8, 8, fake, fake, fake, fake, -1, ctypes.byref(n), None,
                                     fake, ws, None) == -1
+    # fused tree + pairs: kind, n_pairs, capacity, workspace
+    assert lib.mt_build_pairs(fake, 8, 8, 8, 2, fake, fake, fake, fake, fake, 10, ctypes.byref(n), None, fake, ws,
+                              None) == -1
+    assert lib.mt_build_pairs(fake, 8, 8, 8, 0, fake, fake, fake, fake, fake, 10, None, None, fake, ws, None) == -1
+    assert lib.mt_build_pairs(fake, 8, 8, 8, 0, fake, fake, fake, fake, fake, -1, ctypes.byref(n), None, fake, ws,
+                              None) == -1
+    assert lib.mt_build_pairs(fake, 8, 8, 8, 0, fake, None, None, None, None, 10, ctypes.byref(n), None, fake, ws,
+                              None) == -1
+    assert lib.mt_build_pairs(fake, 8, 8, 8, 1, fake, fake, fake, fake, fake, 10, ctypes.byref(n), None, fake,
+                              ws - 1, None) == -6
     # batch: no fields, bad dims
     dims = (ctypes.c_int64 * 3)(8, 0, 8)
     assert lib.mt_batch_build(fake, dims, 1, fake, fake, fake, fake, fake, 10, fake, fake, 1 << 20, None) == -1
