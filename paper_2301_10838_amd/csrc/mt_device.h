@@ -1055,7 +1055,7 @@ __global__ __launch_bounds__(kBlock) void k_repair_min(const float *__restrict__
 // vertices at once, so the dependent loads of their chases (label -> slot ->
 // slot ... -> minimum key) overlap.
 constexpr int RV = 4;
-__global__ __launch_bounds__(kBlock) void k_repair_reg(const float *__restrict__ f, const uint32_t *__restrict__ lbl,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_repair_reg(const float *__restrict__ f, const uint32_t *__restrict__ lbl,
                                                        const Slot *__restrict__ S, const uint64_t *__restrict__ mkey,
                                                        uint64_t *__restrict__ T, uint32_t *__restrict__ pcnt,
                                                        const FieldDesc *__restrict__ D, const int64_t *__restrict__ cs,
@@ -1127,11 +1127,13 @@ __global__ __launch_bounds__(kBlock) void k_repair_reg(const float *__restrict__
         }
         for (uint32_t step = 0; act != 0; ++step) {
             if (step == cap) { err |= ST_LIVELOCK; break; }
+            // all RV loads issued together, no branch around them: a vertex
+            // whose chase has ended reads slot 0 (one shared line per wave)
 #pragma unroll
             for (int i = 0; i < RV; ++i) {
-                if (!((act >> i) & 1u)) continue;
-                tw[i] = S[x[i]].w;
-                tk[i] = S[x[i]].k;
+                const uint32_t xi = ((act >> i) & 1u) ? x[i] : 0u;
+                tw[i] = S[xi].w;
+                tk[i] = S[xi].k;
             }
 #pragma unroll
             for (int i = 0; i < RV; ++i) {
@@ -1223,36 +1225,73 @@ __global__ __launch_bounds__(kBlock) void k_pairs_count(const uint64_t *__restri
 }
 
 // Exclusive scan of the chunk counts (one workgroup of 1024), the total, and
-// the per-field pair offsets.
+// the per-field pair offsets.  Thread t owns a contiguous run of `per` counts
+// (a multiple of 4, so its 16-byte words are aligned), read with all words in
+// flight; the run sums are scanned with wave shuffles and one LDS round.
 __global__ __launch_bounds__(1024) void k_pairs_scan(uint32_t *__restrict__ cnt, int64_t n_chunks,
                                                      const FieldDesc *__restrict__ D, int nf,
                                                      int64_t *__restrict__ pair_offsets, int64_t capacity,
                                                      Header *__restrict__ h)
 {
-    __shared__ uint64_t part[1024];
-    const int tid = threadIdx.x;
-    const int64_t per = (n_chunks + 1023) / 1024;
+    constexpr int NT = 1024, V = 8;  // 16-byte words per thread and round
+    __shared__ uint64_t wtot[NT / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t per = (((n_chunks + NT - 1) / NT) + 3) & ~(int64_t)3;
     const int64_t a = min((int64_t)tid * per, n_chunks), b = min(a + per, n_chunks);
+    auto word = [&](int64_t i) -> uint4 {  // counts i .. i+3, zero past b
+        if (i + 4 <= b) return *(const uint4 *)(cnt + i);
+        uint4 q = make_uint4(0, 0, 0, 0);
+        if (i < b) q.x = cnt[i];
+        if (i + 1 < b) q.y = cnt[i + 1];
+        if (i + 2 < b) q.z = cnt[i + 2];
+        return q;
+    };
     uint64_t s = 0;
-    for (int64_t i = a; i < b; ++i) s += cnt[i];
-    part[tid] = s;
+    for (int64_t i0 = a; i0 < b; i0 += 4 * V) {
+        uint4 q[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) q[v] = word(i0 + 4 * v);
+#pragma unroll
+        for (int v = 0; v < V; ++v) s += (uint64_t)q[v].x + q[v].y + q[v].z + q[v].w;
+    }
+    uint64_t inc = s;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint64_t t = __shfl_up(inc, o);
+        if (lane >= o) inc += t;
+    }
+    if (lane == 63) wtot[wave] = inc;
     __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-        const uint64_t v = tid >= o ? part[tid - o] : 0;
-        __syncthreads();
-        part[tid] += v;
-        __syncthreads();
+    uint64_t run = inc - s, total = 0;
+    for (int w = 0; w < NT / 64; ++w) {
+        const uint64_t t = wtot[w];
+        run += w < wave ? t : 0;
+        total += t;
     }
-    uint64_t run = part[tid] - s;
-    for (int64_t i = a; i < b; ++i) {
-        const uint32_t v = cnt[i];
-        cnt[i] = (uint32_t)run;
-        run += v;
+    for (int64_t i0 = a; i0 < b; i0 += 4 * V) {
+        uint4 q[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) q[v] = word(i0 + 4 * v);
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const int64_t i = i0 + 4 * v;
+            uint4 o;
+            o.x = (uint32_t)run; run += q[v].x;
+            o.y = (uint32_t)run; run += q[v].y;
+            o.z = (uint32_t)run; run += q[v].z;
+            o.w = (uint32_t)run; run += q[v].w;
+            if (i + 4 <= b) {
+                *(uint4 *)(cnt + i) = o;
+            } else {
+                if (i < b) cnt[i] = o.x;
+                if (i + 1 < b) cnt[i + 1] = o.y;
+                if (i + 2 < b) cnt[i + 2] = o.z;
+            }
+        }
     }
-    const uint64_t total = part[1023];
     __syncthreads();
     if (pair_offsets) {
-        for (int i = tid; i < nf; i += 1024) pair_offsets[i] = cnt[D[i].chunk_start];
+        for (int i = tid; i < nf; i += NT) pair_offsets[i] = cnt[D[i].chunk_start];
         if (tid == 0) pair_offsets[nf] = (int64_t)total;
     }
     if (tid == 0) {
