@@ -504,19 +504,30 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
             if (valid(lx, ly, lz) && wl[p] != p) act |= 1u << k;
         }
         const uint32_t moved = act;
+        // every read is issued, with no branch around it: a finished chain
+        // sits on its minimum, which points at itself, and a position outside
+        // the field reads an entry of the tile that is then discarded
         for (int step = 0; act != 0 && step < VOL; ++step) {
             int ys[PER];
 #pragma unroll
-            for (int k = 0; k < PER; ++k) ys[k] = (act >> k) & 1u ? (int)wl[xs[k]] : xs[k];
+            for (int k = 0; k < PER; ++k) {
+                const int y = wl[xs[k]];
+                ys[k] = (act >> k) & 1u ? y : xs[k];
+            }
 #pragma unroll
             for (int k = 0; k < PER; ++k) {
                 if (ys[k] == xs[k]) act &= ~(1u << k);
                 xs[k] = ys[k];
             }
         }
+        // minima's numbers first, then the writes (they go to vertices that are
+        // no minima, so no read sees them)
+        uint16_t zz[PER];
+#pragma unroll
+        for (int k = 0; k < PER; ++k) zz[k] = zl[xs[k]];
 #pragma unroll
         for (int k = 0; k < PER; ++k)
-            if ((moved >> k) & 1u) zl[k * NT + threadIdx.x] = zl[xs[k]];
+            if ((moved >> k) & 1u) zl[k * NT + threadIdx.x] = zz[k];
     }
     __syncthreads();
     const uint32_t b0 = sb0;
@@ -646,24 +657,47 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
     // at its own level (the deepest vertex it is connected to inside the tile
     // at that level).  Later merges and chases start there: the links below
     // the vertex's level are already followed.
-    for (int p = threadIdx.x; p < VOL; p += NT) {
-        const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
-        if (!valid(lx, ly, lz)) continue;
-        uint32_t x = zl[p];
-        if (x >= cnt) { err |= ST_CORRUPT; continue; }
-        const uint64_t level = lkey<PB>(hk, p);
-        for (uint32_t step = 0; step < cap; ++step) {
-            const uint64_t t = TL[x];
-            const uint32_t v = L::tgt(t);
-            if (v >= cnt) { err |= ST_CORRUPT; break; }
-            if (v == x || L::key(t) > level) break;
-            x = v;
+    // (the PER chases of a lane advance together, so their loads overlap)
+    {
+        uint32_t xs[PER], act = 0;
+        uint64_t lv[PER];
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int p = k * NT + threadIdx.x;
+            const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
+            xs[k] = zl[p];
+            lv[k] = lkey<PB>(hk, p);
+            if (!valid(lx, ly, lz)) { xs[k] = 0; continue; }
+            if (xs[k] >= cnt) { err |= ST_CORRUPT; xs[k] = 0; continue; }
+            act |= 1u << k;
         }
-        lbl[gid(p)] = b0 + x;
-        // the first and last x columns also go to the tile's face record
-        // (order key << 32 | label), read contiguously by the cross pass
-        if (lx == 0 || lx == TX - 1)
-            xface[((size_t)c.t * 2 + (lx != 0)) * kXFace + ly + TY * lz] = ((uint64_t)hk[p] << 32) | (b0 + x);
+        const uint32_t live = act;
+        for (uint32_t step = 0; act != 0; ++step) {
+            if (step == cap) { err |= ST_LIVELOCK; break; }
+            uint64_t t[PER];
+#pragma unroll
+            for (int k = 0; k < PER; ++k) t[k] = TL[xs[k]];  // in range: checked or 0
+#pragma unroll
+            for (int k = 0; k < PER; ++k) {
+                if (!((act >> k) & 1u)) continue;
+                const uint32_t v = L::tgt(t[k]);
+                if (v >= cnt) { err |= ST_CORRUPT; act &= ~(1u << k); continue; }
+                if (v == xs[k] || L::key(t[k]) > lv[k]) act &= ~(1u << k);
+                else xs[k] = v;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            if (!((live >> k) & 1u)) continue;
+            const int p = k * NT + threadIdx.x;
+            const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
+            lbl[gid(p)] = b0 + xs[k];
+            // the first and last x columns also go to the tile's face record
+            // (order key << 32 | label), read contiguously by the cross pass
+            if (lx == 0 || lx == TX - 1)
+                xface[((size_t)c.t * 2 + (lx != 0)) * kXFace + ly + TY * lz] =
+                    ((uint64_t)hk[p] << 32) | (b0 + xs[k]);
+        }
     }
     if (err) atomicOr(&h->status, err);
 }
