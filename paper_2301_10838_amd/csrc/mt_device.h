@@ -117,7 +117,7 @@ struct Fact {
     uint64_t ks;
 };
 
-struct Slot {
+struct alignas(16) Slot {
     uint64_t w;  // (saddle id, target number): the triplet
     uint64_t k;  // order key of the saddle, valid if its low half equals w's saddle
 };
@@ -159,15 +159,20 @@ __device__ __forceinline__ void st_relaxed(T *p, T v)
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
 }
 
-// Both words of a slot, read together (two independent loads, one trip).
+// Both words of a slot, read together.
 struct SlotRead {
     uint64_t w, k;
 };
 __device__ __forceinline__ SlotRead ld_slot(Slot *__restrict__ S, uint32_t x)
 {
+    // One aligned 16-byte load: each 8-byte word arrives whole; the two may
+    // come from different moments, which the id check on k absorbs.  Every
+    // reload of an unchanged slot follows a compare-and-swap on the slots,
+    // so no earlier read can stand in for it.
+    const Slot v = S[x];
     SlotRead r;
-    r.w = ld_relaxed(&S[x].w);
-    r.k = ld_relaxed(&S[x].k);
+    r.w = v.w;
+    r.k = v.k;
     return r;
 }
 
