@@ -454,6 +454,10 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
     constexpr int NW = NT / 64;
     static_assert(VOL / 64 <= 64, "one wave scans the counts");
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // First minimum number of the tile, reserved by one global atomic whose
+    // result is only published (sb0) before the slot writes, so no wave waits
+    // for it in between.
+    uint32_t gbase = 0;
     {
         bool is_min[PER];
         uint64_t mb[PER];
@@ -477,7 +481,10 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
             if (lane < VOL / 64) wsum[lane] = inc - own;
             if (lane == 63) {
                 scnt = inc;
-                sb0 = atomicAdd(&h->n_minima, inc);
+                // (the address is written per lane, offset 0 here, so the
+                // compiler keeps the atomic as issued instead of turning it
+                // into a wave-wide one whose result it must wait for at once)
+                gbase = atomicAdd(&h->n_minima + (threadIdx.x - 63u), inc);
                 nwin = 0;
             }
         }
@@ -535,11 +542,6 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
             if ((moved >> k) & 1u) zl[k * NT + threadIdx.x] = zz[k];
     }
     __syncthreads();
-    const uint32_t b0 = sb0;
-    if (b0 + cnt > mcap || b0 + cnt < b0) {  // cannot happen: capacity bounds the minima
-        if (threadIdx.x == 0) atomicOr(&h->status, ST_CORRUPT);
-        return;
-    }
     for (int i = threadIdx.x; i < H; i += NT) htab[i] = ~0ull;
     __syncthreads();
 
@@ -648,7 +650,13 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
         if (x != L::tgt(t))
             __hip_atomic_store(TL + i, L::make(ks, x), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
+    if (threadIdx.x == 63) sb0 = gbase;
     __syncthreads();
+    const uint32_t b0 = sb0;
+    if (b0 + cnt > mcap || b0 + cnt < b0) {  // cannot happen: capacity bounds the minima
+        if (threadIdx.x == 0) atomicOr(&h->status, ST_CORRUPT);
+        return;
+    }
 
     for (uint32_t i = threadIdx.x; i < cnt; i += NT) {
         const uint64_t t = TL[i];
