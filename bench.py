@@ -1,13 +1,14 @@
 """Benchmark of the triplet merge tree path on one MI355X.
 
 One step = the whole single-field hot path on the 512^3 log-normal k^-3 field
-(merge tree with mt_build, then persistence pairs with mt_persistence_pairs,
-which synchronizes to return the pair count), with the field already resident
-in HBM.  Prints one JSON line.
+(merge tree and persistence pairs in one mt_build_pairs call, which
+synchronizes to return the pair count), with the field already resident in
+HBM.  Prints one JSON line.
 
 Also reported (under "secondary"): the uneven 48-field batch in one graph
-launch against 48 plain calls, and the backward scatter of a 16 x 128^3
-differentiable batch.
+launch against 48 plain calls, the backward scatter of a 16 x 128^3
+differentiable batch, the split tree of the timed field, and the global sort
+a rank-keyed build would start with (mt_vertex_ranks) set against the step.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
@@ -266,6 +267,38 @@ def bench_split(ft, lib, mt, s, steps: int = 5):
             "pairs": s.np.value, "equals_merge_tree_of_negated_field": same}
 
 
+def bench_ranks(ft, lib, mt, step_ms: float, steps: int = 5):
+    """The first step of a rank-keyed build (every vertex's position in the
+    (value, id) order: order keys, one global radix sort, positions back) on
+    the timed field, set against the whole value-keyed step."""
+    import torch
+
+    nx, ny, nz = mt.grid_dims(ft.shape)
+    ws = mt.alloc_workspace(lib.mt_rank_workspace_bytes(nx, ny, nz), ft.device)
+    r = torch.empty(ft.numel(), dtype=torch.int32, device=ft.device)
+    st = torch.cuda.current_stream(ft.device).cuda_stream
+
+    def step():
+        rc = lib.mt_vertex_ranks(ft.data_ptr(), nx, ny, nz, mt.MT_TREE_MERGE, r.data_ptr(), ws.data_ptr(),
+                                 ws.numel(), st)
+        if rc != 0:
+            raise mt.MTError(rc, "mt_vertex_ranks")
+
+    step()
+    torch.cuda.synchronize()
+    mt.profile_begin()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    ks = mt.profile_end()
+    sort_ms = ks["radix_sort"][0] / ks["radix_sort"][1] if "radix_sort" in ks else None
+    del ws, r
+    return {"workload": "grf512 vertex ranks", "ms": dt * 1e3, "radix_sort_ms": sort_ms,
+            "over_value_keyed_step": dt * 1e3 / step_ms}
+
+
 def bench_backward(dev, mt, steps: int = 20):
     import torch
 
@@ -473,7 +506,8 @@ def main():
         del src, dst
     if not args.no_secondary:
         out["secondary"] = {"batched": bench_batch(dev, mt, lib), "backward": bench_backward(dev, mt),
-                            "split_tree": bench_split(ft, lib, mt, s)}
+                            "split_tree": bench_split(ft, lib, mt, s),
+                            "rank_keys": bench_ranks(ft, lib, mt, dt * 1e3)}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(f, dev, mt, lib)
     print(json.dumps(out), flush=True)

@@ -197,6 +197,27 @@ int mt_batch_build_tree(const float *fields, const int64_t *dims, int32_t n_fiel
                         int64_t *pair_offsets, void *workspace, size_t ws_bytes, void *stream);
 
 /*
+ * mt_vertex_ranks -- every vertex's position in the order of Sec. 2 (value,
+ * then id; kind as in mt_build_tree: MT_TREE_SPLIT ranks -f): ranks[u] = the
+ * number of vertices that precede u.  The first step of a rank-keyed build
+ * (one global sort, after which every order test is an integer compare); it
+ * is exported so that its cost can be measured against the value-keyed build.
+ *
+ * field (device) float[nx*ny*nz], read only.  ranks (device) uint32[N],
+ * written.  workspace (device) at least mt_rank_workspace_bytes(nx, ny, nz)
+ * bytes, 256-byte aligned (order keys, their sorted copy, sort scratch).
+ * Steps on `stream`, asynchronous: order keys (value key << 32 | id), one
+ * radix sort of the 64-bit keys, positions scattered back.
+ * Errors: MT_ERR_INVALID_ARG, MT_ERR_TOO_LARGE, MT_ERR_WORKSPACE, MT_ERR_HIP
+ * synchronously; MT_ERR_NAN latched (read it with mt_sync_status).
+ */
+int mt_vertex_ranks(const float *field, int64_t nx, int64_t ny, int64_t nz, int kind,
+                    uint32_t *ranks, void *workspace, size_t ws_bytes, void *stream);
+
+/* Bytes of device workspace mt_vertex_ranks needs; 0 if the dims are invalid. */
+size_t mt_rank_workspace_bytes(int64_t nx, int64_t ny, int64_t nz);
+
+/*
  * mt_sync_status -- synchronize `stream` and return the status latched in
  * `workspace` by the work enqueued before (MT_OK if none).  n_pairs and
  * n_roots (host, may be NULL) receive the totals of the last pairs readout

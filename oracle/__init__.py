@@ -12,6 +12,7 @@ Functions (each follows the passage cited in ``oracle.c``):
 - ``pairs(f, T)``: zero-dimensional persistence pairs, one per branch (Sec. 1).
 - ``pairs_scatter``: chain rule of a loss on the pair values (double).
 - ``topo_loss(f, tau)``: the simplification loss and its gradient (double).
+- ``vertex_ranks(f)``: each vertex's position in the (value, id) order (Sec. 2).
 
 Every value is handled in double precision; float32 fields are widened
 exactly before the call, which keeps the order of values unchanged.
@@ -65,6 +66,8 @@ def _load():
         lib.oracle_pairs_scatter.restype = ctypes.c_int
         lib.oracle_topo_loss.argtypes = [P, I64, I64, I64, ctypes.c_double, P, P]
         lib.oracle_topo_loss.restype = ctypes.c_int
+        lib.oracle_vertex_ranks.argtypes = [P, I64, P]
+        lib.oracle_vertex_ranks.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -144,6 +147,16 @@ def topo_loss(f, tau: float, want_grad: bool = True):
     if st != OK:
         raise OracleError(st, "topo_loss")
     return float(loss.value), g
+
+
+def vertex_ranks(f) -> np.ndarray:
+    """rank[u] = number of vertices preceding u in the (value, id) order; uint32 [N]."""
+    f64 = _as_f64(f).reshape(-1)
+    r = np.empty(f64.size, np.uint32)
+    st = _load().oracle_vertex_ranks(f64.ctypes.data, f64.size, r.ctypes.data)
+    if st != OK:
+        raise OracleError(st, "vertex_ranks")
+    return r
 
 
 def build_batch(fields):

@@ -107,6 +107,29 @@ static int validate(int64_t nx, int64_t ny, int64_t nz)
 }
 
 /*
+ * Rank of every vertex in the total order above (Sec. 2: value, then id):
+ * rank[u] = the number of vertices that precede u.  These are the keys a
+ * rank-keyed build would compare instead of values.
+ */
+int oracle_vertex_ranks(const double *f, int64_t N, uint32_t *rank)
+{
+    if (!f || !rank || N < 1) return OR_ERR_INVALID_ARG;
+    if (N >= (1LL << 31)) return OR_ERR_TOO_LARGE;
+    for (int64_t i = 0; i < N; ++i)
+        if (isnan(f[i])) return OR_ERR_NAN;
+    keyed *order = (keyed *)malloc((size_t)N * sizeof(keyed));
+    if (!order) return OR_ERR_NOMEM;
+    for (int64_t i = 0; i < N; ++i) {
+        order[i].val = f[i];
+        order[i].id = (uint32_t)i;
+    }
+    qsort(order, (size_t)N, sizeof(keyed), cmp_keyed);
+    for (int64_t i = 0; i < N; ++i) rank[order[i].id] = (uint32_t)i;
+    free(order);
+    return OR_OK;
+}
+
+/*
  * Merge tree of f by the sorted union-find sweep of Sec. 2.1, written out as
  * its triplet representation (Sec. 2).  T receives 2*N uint32: T[2u] = s,
  * T[2u+1] = v.

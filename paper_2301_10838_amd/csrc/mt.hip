@@ -21,6 +21,8 @@
 #include <unordered_map>
 #include <vector>
 
+#include <rocprim/device/device_radix_sort.hpp>
+
 #include "mt.h"
 #include "mt_device.h"
 
@@ -640,6 +642,67 @@ int mt_sync_status(const void *workspace, void *stream, int64_t *n_pairs, int64_
     if (n_pairs) *n_pairs = h.total_pairs;
     if (n_roots) *n_roots = h.roots;
     return status_to_code(h.status);
+}
+
+// Vertex ranks --------------------------------------------------------------
+
+namespace {
+struct RankLayout {
+    size_t keys = 0, sorted = 0, tmp = 0, tmp_bytes = 0, total = 0;
+};
+
+int rank_layout(int64_t nx, int64_t ny, int64_t nz, RankLayout &L)
+{
+    if (nx < 1 || ny < 1 || nz < 1) return MT_ERR_INVALID_ARG;
+    if (nx >= (1LL << 31) || ny >= (1LL << 31) || nz >= (1LL << 31) || nx * ny >= (1LL << 31) ||
+        nx * ny * nz >= (1LL << 31))
+        return MT_ERR_TOO_LARGE;
+    const size_t n = (size_t)(nx * ny * nz);
+    size_t tmp = 0;  // a size query: nothing is launched
+    if (rocprim::radix_sort_keys(nullptr, tmp, (const uint64_t *)nullptr, (uint64_t *)nullptr, n, 0, 64) !=
+        hipSuccess)
+        return MT_ERR_HIP;
+    size_t o = align256(sizeof(Header));
+    L.keys = o; o = align256(o + sizeof(uint64_t) * n);
+    L.sorted = o; o = align256(o + sizeof(uint64_t) * n);
+    L.tmp = o; L.tmp_bytes = tmp; o = align256(o + std::max<size_t>(tmp, 1));
+    L.total = o;
+    return MT_OK;
+}
+}  // namespace
+
+size_t mt_rank_workspace_bytes(int64_t nx, int64_t ny, int64_t nz)
+{
+    RankLayout L;
+    return rank_layout(nx, ny, nz, L) == MT_OK ? L.total : 0;
+}
+
+int mt_vertex_ranks(const float *field, int64_t nx, int64_t ny, int64_t nz, int kind, uint32_t *ranks,
+                    void *workspace, size_t ws_bytes, void *stream)
+{
+    if (kind != MT_TREE_MERGE && kind != MT_TREE_SPLIT) return MT_ERR_INVALID_ARG;
+    RankLayout L;
+    const int rc = rank_layout(nx, ny, nz, L);
+    if (rc != MT_OK) return rc;
+    if (!field || !ranks) return MT_ERR_INVALID_ARG;
+    if (!workspace || ((uintptr_t)workspace & 255u) || ws_bytes < L.total) return MT_ERR_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    char *b = (char *)workspace;
+    Header *h = (Header *)b;
+    const uint32_t n = (uint32_t)(nx * ny * nz);
+    uint64_t *keys = (uint64_t *)(b + L.keys), *sorted = (uint64_t *)(b + L.sorted);
+    const unsigned g = (unsigned)std::min<int64_t>(8192, ((int64_t)n + kBlock - 1) / kBlock);
+    MT_LAUNCH("k_zero32", k_zero32, dim3(1), dim3(kBlock), st, (uint32_t *)h, (int64_t)(sizeof(Header) / 4));
+    MT_LAUNCH("k_rank_keys", k_rank_keys, dim3(g), dim3(kBlock), st, field, n, kind_flip(kind), keys, h);
+    {
+        ProfScope ps_("radix_sort", st);
+        size_t tb = L.tmp_bytes;
+        if (rocprim::radix_sort_keys((void *)(b + L.tmp), tb, (const uint64_t *)keys, sorted, (size_t)n, 0, 64,
+                                     st) != hipSuccess)
+            return MT_ERR_HIP;
+    }
+    MT_LAUNCH("k_rank_scatter", k_rank_scatter, dim3(g), dim3(kBlock), st, (const uint64_t *)sorted, n, ranks);
+    return MT_OK;
 }
 
 int mt_tile_shape_count(void) { return kNumShapes; }

@@ -1441,6 +1441,31 @@ __global__ __launch_bounds__(kBlock) void k_pairs_write(const float *__restrict_
 }
 
 // ---------------------------------------------------------------------------
+// Vertex ranks: the (value, id) order of Sec. 2 as integer keys, the first
+// step of a rank-keyed build (order keys, one radix sort, positions back).
+
+__global__ __launch_bounds__(kBlock) void k_rank_keys(const float *__restrict__ f, uint32_t n, uint32_t flip,
+                                                      uint64_t *__restrict__ keys, Header *__restrict__ h)
+{
+    bool nan = false;
+    for (uint32_t u = blockIdx.x * kBlock + threadIdx.x; u < n; u += gridDim.x * kBlock) {
+        const float x = f[u];
+        nan |= x != x;
+        keys[u] = vkey(f, u, flip);
+    }
+    if (__ballot(nan) != 0ull && (threadIdx.x & 63) == 0) atomicOr(&h->status, ST_NAN);
+}
+
+__global__ __launch_bounds__(kBlock) void k_rank_scatter(const uint64_t *__restrict__ sorted, uint32_t n,
+                                                         uint32_t *__restrict__ rank)
+{
+    for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        const uint32_t u = lo32(sorted[i]);
+        if (u < n) rank[u] = i;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // 6. Adjoint of the pair readout
 
 __global__ void k_fill0(float *__restrict__ g, int64_t n)

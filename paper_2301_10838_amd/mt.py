@@ -32,7 +32,7 @@ EXPORTS = [
     "mt_profile_begin",
     "mt_profile_end", "mt_profile_count", "mt_profile_get", "mt_tile_shape_count", "mt_tile_shape_info",
     "mt_set_tile_shape", "mt_get_tile_shape", "mt_autotune_workspace_bytes", "mt_autotune", "mt_build_tree",
-    "mt_batch_build_tree", "mt_build_pairs",
+    "mt_batch_build_tree", "mt_build_pairs", "mt_vertex_ranks", "mt_rank_workspace_bytes",
 ]
 
 # tree kinds (include/mt.h)
@@ -80,6 +80,10 @@ def load_library():
     lib.mt_persistence_pairs.restype = ctypes.c_int
     lib.mt_build_pairs.argtypes = [P, I64, I64, I64, ctypes.c_int, P, P, P, P, P, I64, P, P, P, SZ, P]
     lib.mt_build_pairs.restype = ctypes.c_int
+    lib.mt_vertex_ranks.argtypes = [P, I64, I64, I64, ctypes.c_int, P, P, SZ, P]
+    lib.mt_vertex_ranks.restype = ctypes.c_int
+    lib.mt_rank_workspace_bytes.argtypes = [I64, I64, I64]
+    lib.mt_rank_workspace_bytes.restype = SZ
     lib.mt_batch_build.argtypes = [P, P, I32, P, P, P, P, P, I64, P, P, SZ, P]
     lib.mt_batch_build.restype = ctypes.c_int
     lib.mt_batch_build_tree.argtypes = [P, P, I32, ctypes.c_int, P, P, P, P, P, I64, P, P, SZ, P]
@@ -227,6 +231,35 @@ def mt_build_pairs(field: torch.Tensor, kind="merge", capacity: int | None = Non
     _check(rc, "mt_build_pairs")
     P = n_pairs.value
     return triplets, birth[:P], death[:P], bval[:P], dval[:P], n_roots.value
+
+
+def mt_vertex_ranks(field: torch.Tensor, kind="merge", ranks: torch.Tensor | None = None,
+                    workspace: torch.Tensor | None = None) -> torch.Tensor:
+    """Position of every vertex in the (value, id) order (of -f for kind
+    "split"): int32 [N] holding uint32 ranks.  Asynchronous; a NaN is reported
+    by mt_sync_status on the workspace."""
+    lib = load_library()
+    f = _field(field)
+    nx, ny, nz = grid_dims(f.shape)
+    N = nx * ny * nz
+    if ranks is None:
+        ranks = torch.empty(N, dtype=torch.int32, device=f.device)
+    if workspace is None:
+        workspace = alloc_workspace(lib.mt_rank_workspace_bytes(nx, ny, nz), f.device)
+    rc = lib.mt_vertex_ranks(f.data_ptr(), nx, ny, nz, _kind(kind), ranks.data_ptr(), workspace.data_ptr(),
+                             workspace.numel(), _stream_ptr(f.device))
+    _check(rc, "mt_vertex_ranks")
+    return ranks
+
+
+def sync_status(workspace: torch.Tensor):
+    """Status latched in a workspace by the work enqueued before: (n_pairs, n_roots); raises on error."""
+    lib = load_library()
+    n_pairs, n_roots = ctypes.c_int64(0), ctypes.c_int64(0)
+    rc = lib.mt_sync_status(workspace.data_ptr(), _stream_ptr(workspace.device), ctypes.byref(n_pairs),
+                            ctypes.byref(n_roots))
+    _check(rc, "mt_sync_status")
+    return n_pairs.value, n_roots.value
 
 
 class BatchPlan:

@@ -84,6 +84,16 @@ def test_host_argument_checks(lib):
                               None) == -1
     assert lib.mt_build_pairs(fake, 8, 8, 8, 1, fake, fake, fake, fake, fake, 10, ctypes.byref(n), None, fake,
                               ws - 1, None) == -6
+    # vertex ranks: kind, dims, null ranks, workspace
+    rws = lib.mt_rank_workspace_bytes(8, 8, 8)
+    assert rws > 16 * 512 and lib.mt_rank_workspace_bytes(0, 8, 8) == 0
+    assert lib.mt_rank_workspace_bytes(1 << 16, 1 << 15, 1) == 0
+    assert lib.mt_vertex_ranks(fake, 8, 8, 8, 2, fake, fake, rws, None) == -1
+    assert lib.mt_vertex_ranks(fake, 8, 0, 8, 0, fake, fake, rws, None) == -1
+    assert lib.mt_vertex_ranks(fake, 1 << 16, 1 << 15, 1, 0, fake, fake, rws, None) == -2
+    assert lib.mt_vertex_ranks(fake, 8, 8, 8, 0, None, fake, rws, None) == -1
+    assert lib.mt_vertex_ranks(fake, 8, 8, 8, 1, fake, fake, rws - 1, None) == -6
+    assert lib.mt_vertex_ranks(fake, 8, 8, 8, 1, fake, ctypes.c_void_p(0x10010), rws, None) == -6
     # batch: no fields, bad dims
     dims = (ctypes.c_int64 * 3)(8, 0, 8)
     assert lib.mt_batch_build(fake, dims, 1, fake, fake, fake, fake, fake, 10, fake, fake, 1 << 20, None) == -1

@@ -317,3 +317,36 @@ def test_empty_rejected():
 def test_single_vertex():
     T = oracle.merge_tree(np.array([3.0], np.float32))
     assert T.tolist() == [[0, 0]]
+
+
+# --- vertex ranks (the (value, id) order of Sec. 2 as integer keys) ---------
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_vertex_ranks_brute_force(seed):
+    """rank[u] = #{w : f[w] < f[u] or (f[w] == f[u] and w < u)}, counted
+    directly on small fields with repeated values and both signed zeros."""
+    rng = np.random.default_rng(seed)
+    f = rng.integers(-3, 4, 400).astype(np.float32)
+    f[rng.random(400) < 0.1] = -0.0
+    f[rng.random(400) < 0.05] = np.inf
+    r = oracle.vertex_ranks(f)
+    fv = f.astype(np.float64)
+    ids = np.arange(f.size)
+    before = (fv[None, :] < fv[:, None]) | ((fv[None, :] == fv[:, None]) & (ids[None, :] < ids[:, None]))
+    assert np.array_equal(r, before.sum(axis=1).astype(np.uint32))
+
+
+def test_vertex_ranks_permutation_and_reversal():
+    rng = np.random.default_rng(7)
+    f = rng.standard_normal(1000).astype(np.float32)  # distinct values
+    r = oracle.vertex_ranks(f)
+    assert np.array_equal(np.sort(r), np.arange(f.size, dtype=np.uint32))
+    # distinct values: the order of -f is the reverse order
+    assert np.array_equal(oracle.vertex_ranks(-f), (f.size - 1 - r).astype(np.uint32))
+    # a constant field is ordered by id alone
+    assert np.array_equal(oracle.vertex_ranks(np.full(50, 2.5, np.float32)), np.arange(50, dtype=np.uint32))
+
+
+def test_vertex_ranks_nan_rejected():
+    with pytest.raises(oracle.OracleError):
+        oracle.vertex_ranks(np.array([1.0, np.nan], np.float32))
