@@ -692,7 +692,8 @@ int mt_vertex_ranks(const float *field, int64_t nx, int64_t ny, int64_t nz, int 
     const uint32_t n = (uint32_t)(nx * ny * nz);
     uint64_t *keys = (uint64_t *)(b + L.keys), *sorted = (uint64_t *)(b + L.sorted);
     const unsigned g = (unsigned)std::min<int64_t>(8192, ((int64_t)n + kBlock - 1) / kBlock);
-    MT_LAUNCH("k_zero32", k_zero32, dim3(1), dim3(kBlock), st, (uint32_t *)h, (int64_t)(sizeof(Header) / 4));
+    MT_LAUNCH("k_zero32", k_zero32, dim3(grid1d((int64_t)(sizeof(Header) / 4))), dim3(kBlock), st, (uint32_t *)h,
+              (int64_t)(sizeof(Header) / 4));
     MT_LAUNCH("k_rank_keys", k_rank_keys, dim3(g), dim3(kBlock), st, field, n, kind_flip(kind), keys, h);
     {
         ProfScope ps_("radix_sort", st);
@@ -830,7 +831,7 @@ int mt_build_stats(const void *workspace, void *stream, int64_t *n_local_minima,
     *n_local_minima = h.n_minima;
     if (n_cross_facts) {
         int64_t t = 0;
-        for (int x = 0; x < 8; ++x) t += h.n_cross[x];
+        for (int x = 0; x < 8; ++x) t += h.n_cross[x * kXStride];
         *n_cross_facts = t;
     }
     return MT_OK;

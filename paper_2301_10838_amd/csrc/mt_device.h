@@ -101,13 +101,17 @@ struct FieldDesc {
     int64_t chunk_start;     // first chunk (field order)
 };
 
+constexpr int kXStride = 32;  // one 128-byte line per XCD queue counter
 struct Header {
     uint32_t status;
     uint32_t n_minima;       // minimum numbers handed out
     int64_t total_pairs;
     int64_t roots;
-    uint32_t n_cross[8];     // cross-tile facts queued, per XCD
     int64_t reserved[1];
+    // cross-tile facts queued for XCD x at n_cross[x * kXStride]: every
+    // workgroup of an XCD reserves its queue room here, so the counters
+    // stay on lines of their own
+    alignas(128) uint32_t n_cross[8 * kXStride];
 };
 
 // A fact "minima a and b are connected at the level of the saddle whose key
@@ -279,7 +283,7 @@ __global__ void k_setup(SetupArgs a, FieldDesc *D, int32_t *tfield, int64_t *tst
             h->total_pairs = 0;
             h->roots = 0;
             h->n_minima = 0;
-            for (int x = 0; x < 8; ++x) h->n_cross[x] = 0;
+            for (int x = 0; x < 8; ++x) h->n_cross[x * kXStride] = 0;
         }
     }
 }
@@ -894,7 +898,7 @@ __global__ __launch_bounds__(S::NT) void k_cross(const float *__restrict__ f, co
     if (threadIdx.x == 0) {
         uint32_t tot = 0;
         for (int w = 0; w < NT / 64; ++w) tot += wsum[w];
-        sbase = tot ? atomicAdd(&h->n_cross[blockIdx.x % 8], tot) : 0u;
+        sbase = tot ? atomicAdd(&h->n_cross[(blockIdx.x % 8) * kXStride], tot) : 0u;
     }
     __syncthreads();
     uint32_t pos = sbase + incl - mine;
@@ -1011,7 +1015,7 @@ __global__ __launch_bounds__(kBlock) void k_qscatter(const Fact *__restrict__ qu
 {
     __shared__ CounterAgg<2 * kBlock> agg;
     const uint32_t x = blockIdx.x % 8, per = gridDim.x / 8;
-    const uint32_t Q = min(h->n_cross[x], qsub);
+    const uint32_t Q = min(h->n_cross[x * kXStride], qsub);
     const Fact *__restrict__ src = queue + (size_t)x * qsub;
     Fact *__restrict__ dst = qbin + (size_t)x * qsub;
     uint32_t *__restrict__ hist = qhist + (size_t)x * kQCounters;
@@ -1047,7 +1051,7 @@ __global__ __launch_bounds__(kBlock) void k_merge_q(const float *__restrict__ f,
 {
     const uint32_t M = h->n_minima;
     const uint32_t x = blockIdx.x % 8, per = gridDim.x / 8;
-    const uint32_t Q = min(h->n_cross[x], qsub);
+    const uint32_t Q = min(h->n_cross[x * kXStride], qsub);
     const Fact *__restrict__ mq = queue + (size_t)x * qsub;
     uint32_t err = 0;
     for (uint32_t i = (blockIdx.x / 8) * kBlock + threadIdx.x; i < Q; i += per * kBlock) {
