@@ -71,14 +71,14 @@ constexpr int kChunk = 4096;                 // vertices per workgroup in flat p
 constexpr int kSetupMax = 12;                // field descriptors per k_setup launch
 constexpr int kBwdGroup = 64;                // fields per backward launch
 constexpr int kXFace = 256;                  // largest x face of a tile shape (TY * TZ)
-// Cross-tile facts are binned by the top bits of their saddle key (sign,
-// exponent and the top mantissa bit of the value: coarse on purpose, since
-// within a bin the facts keep roughly their queue order, i.e. stay grouped
-// by tile, which keeps the slots that concurrent merges touch close; the
-// lanes in flight span many such bins anyway).  Each bin's counter has
-// kQCopies copies (chosen by the fact's queue position, so the counting and
-// the scattering pass agree), which keeps the atomics on one bin apart.
-constexpr int kQBinBits = 10;
+// Cross-tile facts are binned by the top bits of their saddle key (sign and
+// exponent of the value: coarse on purpose, since within a bin the facts
+// keep roughly their queue order, i.e. stay grouped by tile, which keeps the
+// slots that concurrent merges touch close; the lanes in flight span many
+// such bins anyway).  Each bin's counter has kQCopies copies (chosen by the
+// fact's queue position, so the counting and the scattering pass agree),
+// which keeps the atomics on one bin apart.
+constexpr int kQBinBits = 9;
 constexpr int kQBins = 1 << kQBinBits;
 constexpr int kQCopies = 16;
 constexpr int kQChunkBits = 10;              // queue positions per copy turn
@@ -941,7 +941,7 @@ __global__ void k_zero32(uint32_t *__restrict__ p, int64_t n)
 // launches over kQScanBlocks workgroups per XCD: block totals first, then
 // each block scans its bins from the sum of the blocks before it.  Lane t of
 // a block owns QB bins with all their copies.
-constexpr int kQScanBlocks = 4;
+constexpr int kQScanBlocks = 2;
 constexpr int kQScanThreads = 256;
 constexpr int kQBinsPerBlock = kQBins / kQScanBlocks;
 static_assert(kQBinsPerBlock % kQScanThreads == 0, "whole bins per lane");
