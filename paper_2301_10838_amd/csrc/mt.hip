@@ -336,7 +336,7 @@ template <class S>
 static int launch_cross(const Plan &p, const ClassLaunch &cl, const Ptrs &w, const float *f, uint32_t flip,
                         hipStream_t st)
 {
-    MT_LAUNCH("k_cross", HIP_KERNEL_NAME(k_cross<S>), dim3((unsigned)cl.ntiles), dim3(S::NT), st, f,
+    MT_LAUNCH("k_cross", HIP_KERNEL_NAME(k_cross<S>), dim3((unsigned)cl.ntiles), dim3(cross_threads<S>()), st, f,
               (const uint32_t *)w.lbl, w.queue, (uint32_t)p.q_cap, (const FieldDesc *)w.D,
               (const int32_t *)w.tfield + cl.cb, (const int64_t *)w.tstart + cl.cb, cl.nfc, cl.tile0, cl.ntiles,
               g_remap, w.qhist, (const uint64_t *)w.xface, flip, w.h);

@@ -801,8 +801,13 @@ constexpr int pow2_at_least(int v)
 // are appended to the queue of the XCD this workgroup runs on (one atomic per
 // workgroup) and merged by k_merge_q, where every lane has a merge to do and
 // each XCD works on the facts of its own tiles (so its L2 holds their slots).
+// Workgroup size of the cross pass: at most 512 threads (a tile's faces hold
+// at most 3 x 256 edges), so more workgroups share a CU than in the tile pass.
 template <class S>
-__global__ __launch_bounds__(S::NT) void k_cross(const float *__restrict__ f, const uint32_t *__restrict__ lbl,
+constexpr int cross_threads() { return S::NT < 512 ? S::NT : 512; }
+
+template <class S>
+__global__ __launch_bounds__(cross_threads<S>()) void k_cross(const float *__restrict__ f, const uint32_t *__restrict__ lbl,
                                                  Fact *__restrict__ queue, uint32_t qsub,
                                                  const FieldDesc *__restrict__ D, const int32_t *__restrict__ tfield,
                                                  const int64_t *__restrict__ tstart, int nfc, int64_t tile0,
@@ -810,7 +815,7 @@ __global__ __launch_bounds__(S::NT) void k_cross(const float *__restrict__ f, co
                                                  const uint64_t *__restrict__ xface, uint32_t flip,
                                                  Header *__restrict__ h)
 {
-    constexpr int TX = S::TX, TY = S::TY, TZ = S::TZ, NT = S::NT;
+    constexpr int TX = S::TX, TY = S::TY, TZ = S::TZ, NT = cross_threads<S>();
     // faces that can have a neighbour: a 2-D shape has no z face, a 1-D one no y face
     constexpr int FX = TY * TZ, FY = TY > 1 ? TX * TZ : 0, FZ = TZ > 1 ? TX * TY : 0;
     constexpr int E = FX + FY + FZ;
@@ -836,8 +841,11 @@ __global__ __launch_bounds__(S::NT) void k_cross(const float *__restrict__ f, co
     // facts that find no table room are queued as they are (at most one per edge)
     constexpr int kOverflow = (E + NT - 1) / NT;
     Fact over[kOverflow];
-    int nover = 0;
-    for (int e = threadIdx.x; e < E; e += NT) {
+    uint32_t ovf = 0;  // bit r: over[r] holds a fact
+#pragma unroll
+    for (int r = 0; r < kOverflow; ++r) {  // a static index keeps over[] in registers
+        const int e = r * NT + (int)threadIdx.x;
+        if (e >= E) continue;
         int lx, ly, lz;
         int64_t step;
         bool ok;
@@ -881,8 +889,12 @@ __global__ __launch_bounds__(S::NT) void k_cross(const float *__restrict__ f, co
             }
             si = (si + 1) & (H - 1);
         }
-        if (!placed) over[nover++] = Fact{za, zb, ks};
+        if (!placed) {
+            over[r] = Fact{za, zb, ks};
+            ovf |= 1u << r;
+        }
     }
+    const int nover = __builtin_popcount(ovf);
     __syncthreads();
 
     // count this workgroup's facts, reserve queue room with one atomic
@@ -916,7 +928,9 @@ __global__ __launch_bounds__(S::NT) void k_cross(const float *__restrict__ f, co
         }
         ++pos;
     };
-    for (int i = 0; i < nover; ++i) put(over[i]);
+#pragma unroll
+    for (int r = 0; r < kOverflow; ++r)
+        if ((ovf >> r) & 1u) put(over[r]);
     for (int i = threadIdx.x; i < H; i += NT) {
         const uint64_t key = hpair[i];
         if (key != ~0ull) put(Fact{lo32(key), hi32(key), hbest[i]});
