@@ -801,10 +801,11 @@ constexpr int pow2_at_least(int v)
 // are appended to the queue of the XCD this workgroup runs on (one atomic per
 // workgroup) and merged by k_merge_q, where every lane has a merge to do and
 // each XCD works on the facts of its own tiles (so its L2 holds their slots).
-// Workgroup size of the cross pass: at most 512 threads (a tile's faces hold
-// at most 3 x 256 edges), so more workgroups share a CU than in the tile pass.
+// Workgroup size of the cross pass: at most 256 threads (a tile's faces hold
+// at most 3 x 256 edges).  With its small tables that lets eight workgroups
+// share a CU, which overlap each other's queue reservations.
 template <class S>
-constexpr int cross_threads() { return S::NT < 512 ? S::NT : 512; }
+constexpr int cross_threads() { return S::NT < 256 ? S::NT : 256; }
 
 template <class S>
 __global__ __launch_bounds__(cross_threads<S>()) void k_cross(const float *__restrict__ f, const uint32_t *__restrict__ lbl,
@@ -819,12 +820,13 @@ __global__ __launch_bounds__(cross_threads<S>()) void k_cross(const float *__res
     // faces that can have a neighbour: a 2-D shape has no z face, a 1-D one no y face
     constexpr int FX = TY * TZ, FY = TY > 1 ? TX * TZ : 0, FZ = TZ > 1 ? TX * TY : 0;
     constexpr int E = FX + FY + FZ;
-    constexpr int H = pow2_at_least(2 * E) < 2048 ? pow2_at_least(2 * E) : 2048;
+    // pair table: one entry per face edge at most (at least 2, so the hash keeps a bit)
+    constexpr int H = pow2_at_least(E) < 2 ? 2 : pow2_at_least(E) < 2048 ? pow2_at_least(E) : 2048;
     __shared__ uint64_t hpair[H];  // (lower number | higher number << 32)
     __shared__ uint64_t hbest[H];  // lowest upper-end key of an edge joining that pair
     __shared__ uint32_t wsum[NT / 64];
     __shared__ uint32_t sbase;
-    __shared__ CounterAgg<512> agg;
+    __shared__ CounterAgg<256> agg;
     const int64_t tl = xcd_tile(blockIdx.x, gridDim.x, remap);
     if (tl >= ntiles) return;
     const TileCtx c = tile_ctx<S>(D, tfield, tstart, nfc, tile0 + tl);
@@ -936,7 +938,7 @@ __global__ __launch_bounds__(cross_threads<S>()) void k_cross(const float *__res
         if (key != ~0ull) put(Fact{lo32(key), hi32(key), hbest[i]});
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < 512; i += NT)
+    for (int i = threadIdx.x; i < 256; i += NT)
         if (agg.cnt[i]) atomicAdd(hist + agg.key[i], agg.cnt[i]);
     if (err) atomicOr(&h->status, err);
 }
