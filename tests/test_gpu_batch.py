@@ -113,7 +113,7 @@ def test_batch_capacity_latched(dev):
 
 
 def test_batch48_workload(dev):
-    """Full uneven batch: batched == plain for every field, oracle on a subset."""
+    """Full uneven batch: batched == plain and == the oracle for every field."""
     import paper_2301_10838_amd.mt as mt
 
     fs = fields.workload("batch48")
@@ -127,12 +127,19 @@ def test_batch48_workload(dev):
         a, b = plan.vertex_offsets[i], plan.vertex_offsets[i + 1]
         assert np.array_equal(T_all[a:b], T), i
         assert offs[i + 1] - offs[i] == prs[0].size, i
-    small = sorted(range(len(fs)), key=lambda i: fs[i].size)[:10]
-    sub = [fs[i] for i in small]
-    for i in small:
-        f = fs[i]
+    # every field against the oracle: triplets and pairs (about 25 s of one core)
+    b_all, d_all = u32(plan.birth), u32(plan.death)
+    bv_all, dv_all = plan.bval.cpu().numpy(), plan.dval.cpu().numpy()
+    for i, f in enumerate(fs):
         a, b = plan.vertex_offsets[i], plan.vertex_offsets[i + 1]
-        assert np.array_equal(T_all[a:b], oracle.merge_tree(f)), i
+        T_ref = oracle.merge_tree(f)
+        assert np.array_equal(T_all[a:b], T_ref), i
+        rb, rd, rbv, rdv, _ = oracle.pairs(f, T_ref)
+        p0, p1 = offs[i], offs[i + 1]
+        assert np.array_equal(b_all[p0:p1], rb) and np.array_equal(d_all[p0:p1], rd), i
+        flat = f.reshape(-1)
+        assert np.array_equal(bv_all[p0:p1].view(np.uint32), flat[rb].view(np.uint32)), i
+        assert np.array_equal(dv_all[p0:p1].view(np.uint32), flat[rd].view(np.uint32)), i
 
 
 def test_batch_abi_rejects_bad_workspace(dev):
