@@ -132,7 +132,9 @@ int mt_build_tree(const float *field, int64_t nx, int64_t ny, int64_t nz, int ki
  * capacity (then only the first `capacity` are written and the call returns
  * MT_ERR_CAPACITY).  n_roots (host) may be NULL.
  * workspace: as for mt_build; pass the one mt_build used so its latched
- * status (NaN, livelock) is reported here.
+ * status (NaN, livelock) is reported here.  Any other workspace must first be
+ * cleared with mt_workspace_reset, or its leftover bytes may read as a
+ * latched error.
  * Synchronizes `stream` once, to return the counts and the status.
  */
 int mt_persistence_pairs(const float *field, const uint32_t *triplets,
@@ -297,6 +299,81 @@ size_t mt_autotune_workspace_bytes(const int64_t *dims, int32_t n_fields);
 int mt_autotune(const float *fields, const int64_t *dims, int32_t n_fields, uint32_t *triplets,
                 uint32_t *triplets_check, void *workspace, size_t ws_bytes, int reps, void *stream,
                 double *best_ms);
+
+/*
+ * Bounds of the build's loops, for tests of its failure handling and for
+ * tuning.  Both settings are process-wide and are read when a call plans its
+ * launches (a batch graph captured under one setting keeps it; the setting is
+ * part of the graph cache key).
+ *
+ * mt_set_max_steps -- step cap of every merge, descent and chase loop
+ * (Alg. 3, 4, 5 each loop until a condition holds; every kernel bounds them
+ * so that a broken invariant cannot spin forever).  A loop that reaches the
+ * cap stops and latches MT_ERR_LIVELOCK; the triplets are then invalid.
+ * steps = 0 restores the default (2^24); 1 <= steps < 2^31 sets it; anything
+ * else is MT_ERR_INVALID_ARG.  The default is never reached by a valid input:
+ * a merge step moves strictly down a chain of at most N triplets.
+ * mt_get_max_steps returns the cap in force.
+ *
+ * mt_set_table_probes -- probes each edge may spend in the LDS tables that
+ * keep only the lowest edge between two basins (inside a tile, and across a
+ * tile face) before it takes the path that needs no table: merged directly
+ * inside the tile, queued as it is across tiles.  Both paths give the same
+ * triplets; the tables only save merges.  probes = -1 restores the default
+ * (32); 0 <= probes <= 64 sets it (0 sends every edge down the direct path);
+ * anything else is MT_ERR_INVALID_ARG.  mt_get_table_probes returns it.
+ */
+int mt_set_max_steps(int64_t steps);
+int64_t mt_get_max_steps(void);
+int mt_set_table_probes(int probes);
+int mt_get_table_probes(void);
+
+/*
+ * Counting build, for measurement.  mt_set_counting(1) makes every later
+ * call (and newly captured batch graph: the flag is part of its cache key)
+ * launch the counting instantiation of the merge kernels, which tally events
+ * per lane and add them to counters in the workspace head with one atomic per
+ * wave; mt_set_counting(0) (the default) goes back to the timed kernels, in
+ * which every count is compiled out.  The triplets are the same either way.
+ * mt_get_counting returns the flag.
+ *
+ * mt_read_counters synchronizes `stream` and copies the counters of the last
+ * build on `workspace` into counts (host, uint64[n]); it returns how many it
+ * wrote (at most 16; the rest of counts is zeroed) or an error.  In order:
+ *   0 cross-tile merges started (one per queued fact)
+ *   1 iterations of the cross-tile merge loop (Alg. 3)
+ *   2 of those, descent steps
+ *   3 64-bit compare-and-swaps on the minimum slots (Alg. 2)
+ *   4 of those, failed
+ *   5 displaced triplets merged again
+ *   6 most iterations of a single cross-tile merge
+ *   7 merges inside a tile (Alg. 3 in LDS)
+ *   8 iterations of the in-tile merge loop
+ *   9 64-bit LDS compare-and-swaps
+ *  10 of those, failed
+ *  11 most iterations of a single in-tile merge
+ *  12 in-tile edges offered to the table of basin pairs
+ *  13 table probes (one LDS atomic minimum each)
+ *  14 in-tile edges merged without the table
+ *  15 chase steps of the output pass (Alg. 4 for every regular vertex)
+ * Only a counting build writes them; after a timed build they read 0.
+ */
+int mt_set_counting(int on);
+int mt_get_counting(void);
+int mt_read_counters(const void *workspace, void *stream, uint64_t *counts, int n);
+
+/*
+ * mt_workspace_reset -- clear the status word and the counters at the head
+ * of `workspace` (device, 256-byte aligned, ws_bytes long), asynchronously on
+ * `stream`, with a kernel (no memset node, so it may be captured).  A workspace that did not
+ * come out of a build holds arbitrary bytes, and mt_persistence_pairs keeps
+ * the NaN and step-cap bits a build latched there so that it can report them;
+ * call this once on such a workspace before mt_persistence_pairs.  The build
+ * calls clear the head themselves.  Errors: MT_ERR_WORKSPACE (null,
+ * misaligned, or shorter than the head, which every size returned by the
+ * *_workspace_bytes calls exceeds), MT_ERR_HIP.
+ */
+int mt_workspace_reset(void *workspace, size_t ws_bytes, void *stream);
 
 /* Free cached graph plans (device and host memory they hold).  Not safe to
  * call while another thread is inside the library. */

@@ -84,13 +84,21 @@ struct Plan {
     int64_t n_total = 0, n_tiles = 0, n_chunks = 0, m_cap = 0, q_cap = 0;
     ClassLaunch cls[3];
     Layout lay{};
+    // configuration in force when the plan was made
+    int remap = 1;
+    uint32_t cap = 0, probes = 0;
+    int count = 0;
 };
 
-// Configuration (tile shape per class, XCD remap, step cap).
+// Configuration (tile shape per class, XCD remap, step cap, pair-table probes).
 static std::mutex g_cfg_mu;
 static int g_shape[3] = {4, 6, 10};  // 16x16x16, 64x16, 1024
 static int g_remap = 1;
-static uint32_t g_cap = 1u << 24;
+constexpr uint32_t kDefaultCap = 1u << 24;
+constexpr uint32_t kDefaultProbes = 32;
+static uint32_t g_cap = kDefaultCap;
+static uint32_t g_probes = kDefaultProbes;
+static int g_count = 0;  // counting build (event counters) instead of the timed one
 static bool g_env_read = false;
 
 static int find_shape(int cls, int tx, int ty, int tz)
@@ -130,6 +138,10 @@ static int make_plan(const int64_t *dims, int32_t nf, Plan &p, const int *shape_
         std::lock_guard<std::mutex> lk(g_cfg_mu);
         read_env_locked();
         for (int c = 0; c < 3; ++c) shape[c] = shape_override ? shape_override[c] : g_shape[c];
+        p.remap = g_remap;
+        p.cap = g_cap;
+        p.probes = g_probes;
+        p.count = g_count;
     }
     p.d.assign(nf, FieldDesc{});
     p.q_cap = 0;
@@ -322,14 +334,23 @@ static int enqueue_setup(const Plan &p, const Ptrs &w, uint32_t clear_status, bo
     return MT_OK;
 }
 
+template <class S, bool CNT>
+static int launch_local_as(const Plan &p, const ClassLaunch &cl, const Ptrs &w, const float *f, uint32_t flip,
+                           hipStream_t st)
+{
+    auto *const kern = &k_local<S, CNT>;
+    MT_LAUNCH("k_local", kern, dim3((unsigned)cl.ntiles), dim3(S::NT), st, f, w.lbl,
+              w.slot, w.mkey, (const FieldDesc *)w.D, (const int32_t *)w.tfield + cl.cb,
+              (const int64_t *)w.tstart + cl.cb, cl.nfc, cl.tile0, cl.ntiles, p.remap, (uint32_t)p.m_cap, p.cap,
+              w.xface, flip, p.probes, w.h);
+    return MT_OK;
+}
+
 template <class S>
 static int launch_local(const Plan &p, const ClassLaunch &cl, const Ptrs &w, const float *f, uint32_t flip,
                         hipStream_t st)
 {
-    MT_LAUNCH("k_local", HIP_KERNEL_NAME(k_local<S>), dim3((unsigned)cl.ntiles), dim3(S::NT), st, f, w.lbl, w.slot,
-              w.mkey, (const FieldDesc *)w.D, (const int32_t *)w.tfield + cl.cb, (const int64_t *)w.tstart + cl.cb,
-              cl.nfc, cl.tile0, cl.ntiles, g_remap, (uint32_t)p.m_cap, g_cap, w.xface, flip, w.h);
-    return MT_OK;
+    return p.count ? launch_local_as<S, true>(p, cl, w, f, flip, st) : launch_local_as<S, false>(p, cl, w, f, flip, st);
 }
 
 template <class S>
@@ -339,7 +360,7 @@ static int launch_cross(const Plan &p, const ClassLaunch &cl, const Ptrs &w, con
     MT_LAUNCH("k_cross", HIP_KERNEL_NAME(k_cross<S>), dim3((unsigned)cl.ntiles), dim3(cross_threads<S>()), st, f,
               (const uint32_t *)w.lbl, w.queue, (uint32_t)p.q_cap, (const FieldDesc *)w.D,
               (const int32_t *)w.tfield + cl.cb, (const int64_t *)w.tstart + cl.cb, cl.nfc, cl.tile0, cl.ntiles,
-              g_remap, w.qhist, (const uint64_t *)w.xface, flip, w.h);
+              p.remap, w.qhist, (const uint64_t *)w.xface, flip, p.probes, w.h);
     return MT_OK;
 }
 
@@ -372,13 +393,22 @@ static int enqueue_build(const Plan &p, const Ptrs &w, const float *f, uint64_t 
               (const uint32_t *)w.qtot);
     MT_LAUNCH("k_qscatter", k_qscatter, dim3(gq), dim3(kBlock), st, (const Fact *)w.queue, w.qbin,
               (uint32_t)p.q_cap, w.qhist, w.h);
-    MT_LAUNCH("k_merge_q", k_merge_q, dim3(gq), dim3(kBlock), st, f, (const Fact *)w.qbin, (uint32_t)p.q_cap, w.slot,
-              (const uint64_t *)w.mkey, n, g_cap, flip, w.h);
+    if (p.count)
+        MT_LAUNCH("k_merge_q", k_merge_q<true>, dim3(gq), dim3(kBlock), st, f, (const Fact *)w.qbin,
+                  (uint32_t)p.q_cap, w.slot, (const uint64_t *)w.mkey, n, p.cap, flip, w.h);
+    else
+        MT_LAUNCH("k_merge_q", k_merge_q<false>, dim3(gq), dim3(kBlock), st, f, (const Fact *)w.qbin,
+                  (uint32_t)p.q_cap, w.slot, (const uint64_t *)w.mkey, n, p.cap, flip, w.h);
     const unsigned gm = (unsigned)std::min<int64_t>(8192, std::max<int64_t>(1, (p.m_cap + kBlock - 1) / kBlock));
-    MT_LAUNCH("k_repair_min", k_repair_min, dim3(gm), dim3(kBlock), st, f, w.slot, n, g_cap, flip, w.h);
-    MT_LAUNCH("k_repair_reg", k_repair_reg, dim3((unsigned)p.n_chunks), dim3(kBlock), st, f,
-              (const uint32_t *)w.lbl, w.slot, (const uint64_t *)w.mkey, T, w.pcnt, (const FieldDesc *)w.D,
-              (const int64_t *)w.cs, nf, n, g_cap, flip, w.h);
+    MT_LAUNCH("k_repair_min", k_repair_min, dim3(gm), dim3(kBlock), st, f, w.slot, n, p.cap, flip, w.h);
+    if (p.count)
+        MT_LAUNCH("k_repair_reg", k_repair_reg<true>, dim3((unsigned)p.n_chunks), dim3(kBlock), st, f,
+                  (const uint32_t *)w.lbl, w.slot, (const uint64_t *)w.mkey, T, w.pcnt, (const FieldDesc *)w.D,
+                  (const int64_t *)w.cs, nf, n, p.cap, flip, w.h);
+    else
+        MT_LAUNCH("k_repair_reg", k_repair_reg<false>, dim3((unsigned)p.n_chunks), dim3(kBlock), st, f,
+                  (const uint32_t *)w.lbl, w.slot, (const uint64_t *)w.mkey, T, w.pcnt, (const FieldDesc *)w.D,
+                  (const int64_t *)w.cs, nf, n, p.cap, flip, w.h);
     return MT_OK;
 }
 
@@ -595,10 +625,10 @@ int mt_batch_build_tree(const float *fields, const int64_t *dims, int32_t n_fiel
     std::string key;
     key.reserve(96 + 24 * n_fields);
     char buf[320];
-    snprintf(buf, sizeof buf, "%d|%d|%p|%p|%p|%p|%p|%p|%lld|%p|%p|%zu|%d|%u|%d,%d,%d", dev, kind,
+    snprintf(buf, sizeof buf, "%d|%d|%p|%p|%p|%p|%p|%p|%lld|%p|%p|%zu|%d|%u|%u|%d|%d,%d,%d", dev, kind,
              (const void *)fields, (void *)triplets, (void *)birth, (void *)death, (void *)birth_val,
-             (void *)death_val, (long long)pair_capacity, (void *)pair_offsets, workspace, ws_bytes, g_remap, g_cap,
-             p.cls[0].shape, p.cls[1].shape, p.cls[2].shape);
+             (void *)death_val, (long long)pair_capacity, (void *)pair_offsets, workspace, ws_bytes, p.remap, p.cap,
+             p.probes, p.count, p.cls[0].shape, p.cls[1].shape, p.cls[2].shape);
     key += buf;
     for (const FieldDesc &d : p.d) {
         snprintf(buf, sizeof buf, "|%d,%d,%d", d.nx, d.ny, d.nz);
@@ -736,6 +766,76 @@ int mt_get_tile_shape(int dims_class)
     std::lock_guard<std::mutex> lk(g_cfg_mu);
     read_env_locked();
     return g_shape[dims_class];
+}
+
+int mt_set_max_steps(int64_t steps)
+{
+    if (steps < 0 || steps > 0x7fffffffLL) return MT_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(g_cfg_mu);
+    read_env_locked();
+    g_cap = steps == 0 ? kDefaultCap : (uint32_t)steps;
+    return MT_OK;
+}
+
+int64_t mt_get_max_steps(void)
+{
+    std::lock_guard<std::mutex> lk(g_cfg_mu);
+    read_env_locked();
+    return g_cap;
+}
+
+int mt_set_table_probes(int probes)
+{
+    if (probes < -1 || probes > 64) return MT_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(g_cfg_mu);
+    read_env_locked();
+    g_probes = probes < 0 ? kDefaultProbes : (uint32_t)probes;
+    return MT_OK;
+}
+
+int mt_get_table_probes(void)
+{
+    std::lock_guard<std::mutex> lk(g_cfg_mu);
+    read_env_locked();
+    return (int)g_probes;
+}
+
+int mt_set_counting(int on)
+{
+    if (on != 0 && on != 1) return MT_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(g_cfg_mu);
+    read_env_locked();
+    g_count = on;
+    return MT_OK;
+}
+
+int mt_get_counting(void)
+{
+    std::lock_guard<std::mutex> lk(g_cfg_mu);
+    read_env_locked();
+    return g_count;
+}
+
+int mt_read_counters(const void *workspace, void *stream, uint64_t *counts, int n)
+{
+    if (!workspace) return MT_ERR_WORKSPACE;
+    if (!counts || n < 1) return MT_ERR_INVALID_ARG;
+    Header h;
+    const int rc = read_header(workspace, (hipStream_t)stream, h);
+    if (rc != MT_OK) return rc;
+    const int m = std::min(n, (int)kCtr);
+    for (int i = 0; i < m; ++i) counts[i] = h.ctr[i];
+    for (int i = m; i < n; ++i) counts[i] = 0;
+    return m;
+}
+
+int mt_workspace_reset(void *workspace, size_t ws_bytes, void *stream)
+{
+    if (!workspace || ((uintptr_t)workspace & 255u) || ws_bytes < sizeof(Header)) return MT_ERR_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    constexpr int64_t words = (int64_t)(sizeof(Header) / sizeof(uint32_t));
+    MT_LAUNCH("k_zero32", k_zero32, dim3(grid1d(words)), dim3(kBlock), st, (uint32_t *)workspace, words);
+    return MT_OK;
 }
 
 size_t mt_autotune_workspace_bytes(const int64_t *dims, int32_t n_fields)

@@ -101,6 +101,29 @@ struct FieldDesc {
     int64_t chunk_start;     // first chunk (field order)
 };
 
+// Event counts of a counting build (mt_set_counting).  The timed build is a
+// separate instantiation of the same kernels with every count compiled out.
+enum CtrId {
+    C_GM_FACTS,       // cross-tile merges started (one per queued fact)
+    C_GM_STEPS,       // iterations of the cross-tile merge loop
+    C_GM_DESCENTS,    // of those, descent steps (a link followed)
+    C_GM_CAS,         // 64-bit compare-and-swaps on the slots
+    C_GM_CAS_FAIL,    // of those, failed
+    C_GM_REMERGE,     // displaced triplets merged again
+    C_GM_MAX_STEPS,   // most iterations of one cross-tile merge (a maximum)
+    C_LDS_MERGES,     // merges inside a tile
+    C_LDS_STEPS,      // iterations of the in-tile merge loop
+    C_LDS_CAS,        // 64-bit LDS compare-and-swaps
+    C_LDS_CAS_FAIL,   // of those, failed
+    C_LDS_MAX_STEPS,  // most iterations of one in-tile merge (a maximum)
+    C_TAB_INSERTS,    // edges offered to the in-tile pair table
+    C_TAB_PROBES,     // atomic-min probes of those inserts
+    C_TAB_DIRECT,     // edges merged without the table (no room, or no table)
+    C_REG_CHASES,     // chase steps of the output pass
+    kCtr
+};
+__host__ __device__ constexpr bool ctr_is_max(int i) { return i == C_GM_MAX_STEPS || i == C_LDS_MAX_STEPS; }
+
 constexpr int kXStride = 32;  // one 128-byte line per XCD queue counter
 struct Header {
     uint32_t status;
@@ -112,6 +135,44 @@ struct Header {
     // workgroup of an XCD reserves its queue room here, so the counters
     // stay on lines of their own
     alignas(128) uint32_t n_cross[8 * kXStride];
+    alignas(128) unsigned long long ctr[kCtr];  // counting build only
+};
+
+// Per-lane event counts, flushed with one atomic per wave; empty when CNT is
+// false.  flush() must be reached by every lane of the wave.
+template <bool CNT>
+struct Tally {
+    uint32_t v[CNT ? kCtr : 1];
+    __device__ Tally()
+    {
+        if constexpr (CNT)
+            for (int i = 0; i < kCtr; ++i) v[i] = 0;
+    }
+    __device__ __forceinline__ void add(int id, uint32_t x = 1)
+    {
+        if constexpr (CNT) v[id] += x;
+    }
+    __device__ __forceinline__ void max(int id, uint32_t x)
+    {
+        if constexpr (CNT) v[id] = v[id] > x ? v[id] : x;
+    }
+    __device__ void flush(Header *h)
+    {
+        if constexpr (CNT) {
+#pragma unroll
+            for (int i = 0; i < kCtr; ++i) {
+                unsigned long long x = v[i];
+                for (int o = 32; o > 0; o >>= 1) {
+                    const unsigned long long y = __shfl_xor(x, o);
+                    x = ctr_is_max(i) ? (x > y ? x : y) : x + y;
+                }
+                if ((threadIdx.x & 63) == 0 && x) {
+                    if (ctr_is_max(i)) atomicMax(&h->ctr[i], x);
+                    else atomicAdd(&h->ctr[i], x);
+                }
+            }
+        }
+    }
 };
 
 // A fact "minima a and b are connected at the level of the saddle whose key
@@ -163,20 +224,23 @@ __device__ __forceinline__ void st_relaxed(T *p, T v)
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
 }
 
-// Both words of a slot, read together.
+// Both words of a slot.
 struct SlotRead {
     uint64_t w, k;
 };
-__device__ __forceinline__ SlotRead ld_slot(Slot *__restrict__ S, uint32_t x)
+
+// A slot that other lanes may be replacing in the same kernel (the cross-tile
+// merge, the minimum repair): each word is read by its own relaxed atomic
+// load, so it arrives whole; the two may come from different moments, which
+// the id check on k absorbs.  Wavefront scope keeps the read cached: a stale
+// word is a triplet that held earlier and still holds, and the
+// compare-and-swap, which always sees the current word, hands back the fresh
+// one when the read was stale.
+__device__ __forceinline__ SlotRead ld_slot_live(Slot *__restrict__ S, uint32_t x)
 {
-    // One aligned 16-byte load: each 8-byte word arrives whole; the two may
-    // come from different moments, which the id check on k absorbs.  Every
-    // reload of an unchanged slot follows a compare-and-swap on the slots,
-    // so no earlier read can stand in for it.
-    const Slot v = S[x];
     SlotRead r;
-    r.w = v.w;
-    r.k = v.k;
+    r.w = ld_relaxed(&S[x].w);
+    r.k = ld_relaxed(&S[x].k);
     return r;
 }
 
@@ -284,6 +348,7 @@ __global__ void k_setup(SetupArgs a, FieldDesc *D, int32_t *tfield, int64_t *tst
             h->roots = 0;
             h->n_minima = 0;
             for (int x = 0; x < 8; ++x) h->n_cross[x * kXStride] = 0;
+            for (int c = 0; c < kCtr; ++c) h->ctr[c] = 0;
         }
     }
 }
@@ -324,46 +389,52 @@ __device__ __forceinline__ uint64_t lds_ld64(uint64_t *p)
 // tile key is ks".  Descents stop at roots; after a swap that replaced a root
 // nothing was displaced; otherwise the displaced triplet is merged again from
 // the lower minimum; a lost swap restarts with the value it saw.
-template <int VOL>
+template <int VOL, bool CNT>
 __device__ void lds_merge(uint64_t *TL, const uint32_t *hk, const uint16_t *mh, uint32_t u, uint64_t ks,
-                          uint32_t v, uint32_t cnt, uint32_t cap, uint32_t &err)
+                          uint32_t v, uint32_t cnt, uint32_t cap, uint32_t &err, Tally<CNT> &tc)
 {
     using L = LTrip<VOL>;
+    tc.add(C_LDS_MERGES);
     if (u >= cnt || v >= cnt) { err |= ST_CORRUPT; return; }
     uint64_t tu = lds_ld64(TL + u), tv = lds_ld64(TL + v);
-    for (uint32_t step = 0; step < cap; ++step) {
+    uint32_t step = 0;
+    for (; step < cap; ++step) {
         const uint32_t u1 = L::tgt(tu), v1 = L::tgt(tv);
-        if (u1 >= cnt || v1 >= cnt) { err |= ST_CORRUPT; return; }
+        if (u1 >= cnt || v1 >= cnt) { err |= ST_CORRUPT; break; }
         if (u1 != u && L::key(tu) < ks) { u = u1; tu = lds_ld64(TL + u); continue; }
         if (v1 != v && L::key(tv) < ks) { v = v1; tv = lds_ld64(TL + v); continue; }
-        if (u == v) return;
+        if (u == v) break;
         if (lkey<L::PB>(hk, mh[v]) < lkey<L::PB>(hk, mh[u])) {
             const uint32_t w = u; u = v; v = w;
             const uint64_t tw = tu; tu = tv; tv = tw;
         }
         uint64_t seen = tv;
+        tc.add(C_LDS_CAS);
         if (__hip_atomic_compare_exchange_strong(TL + v, &seen, L::make(ks, u), __ATOMIC_RELAXED,
                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) {
-            if (L::tgt(tv) == v) return;
+            if (L::tgt(tv) == v) break;
             ks = L::key(tv);
             v = L::tgt(tv);
             tv = lds_ld64(TL + v);
         } else {
+            tc.add(C_LDS_CAS_FAIL);
             tv = seen;
         }
         tu = lds_ld64(TL + u);
     }
-    err |= ST_LIVELOCK;
+    tc.add(C_LDS_STEPS, step + (step < cap));
+    tc.max(C_LDS_MAX_STEPS, step + (step < cap));
+    if (step == cap) err |= ST_LIVELOCK;
 }
 
-template <class S>
+template <class S, bool CNT>
 __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f, uint32_t *__restrict__ lbl,
                                                  Slot *__restrict__ slot, uint64_t *__restrict__ mkey,
                                                  const FieldDesc *__restrict__ D, const int32_t *__restrict__ tfield,
                                                  const int64_t *__restrict__ tstart, int nfc, int64_t tile0,
                                                  int64_t ntiles, int remap, uint32_t mcap, uint32_t cap,
                                                  uint64_t *__restrict__ xface, uint32_t flip,
-                                                 Header *__restrict__ h)
+                                                 uint32_t probes, Header *__restrict__ h)
 {
     constexpr int NT = S::NT, VOL = S::VOL, TX = S::TX, TY = S::TY;
     static_assert(S::TY * S::TZ <= kXFace, "x face record");
@@ -556,24 +627,30 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
     // lowest edge; an edge that finds no table room is merged directly, and so
     // is every edge of a tile with more minima than a tag can number.
     uint32_t err = 0;
+    Tally<CNT> tc;
     const bool tabled = (uint32_t)HALF <= ZMAX || cnt <= ZMAX;
     // One atomic min per probe: an empty entry is claimed; an entry of the
     // same pair keeps the lower edge; an entry of another pair keeps the
     // lower of the two words and the lane carries the other one on.  Entries
     // move but are never dropped, so every pair's lowest edge ends in the
     // table (or is merged directly); a pair left with a second, higher entry
-    // only costs a merge that changes nothing.
+    // only costs a merge that changes nothing.  `probes` (at most 32 by
+    // default) bounds the probes before the direct merge; a smaller value only
+    // sends more edges down that path.
     auto insert = [&](uint64_t val) {
+        tc.add(C_TAB_INSERTS);
         uint32_t si = ((uint32_t)(val & TAGM) * 0x9E3779B1u) >> (32 - PB);
-        for (int probe = 0; probe < 32; ++probe) {
+        for (uint32_t probe = 0; probe < probes; ++probe) {
+            tc.add(C_TAB_PROBES);
             const uint64_t prev = __hip_atomic_fetch_min(htab + si, val, __ATOMIC_RELAXED,
                                                          __HIP_MEMORY_SCOPE_WORKGROUP);
             if (prev == ~0ull || ((prev ^ val) & TAGM) == 0) return;
             val = prev < val ? val : prev;
             si = (si + 1) & (H - 1);
         }
+        tc.add(C_TAB_DIRECT);
         const uint32_t tag = (uint32_t)(val & TAGM);
-        lds_merge<VOL>(TL, hk, mh, tag & (ZMAX - 1), val >> (2 * ZB), tag >> ZB, cnt, cap, err);
+        lds_merge<VOL, CNT>(TL, hk, mh, tag & (ZMAX - 1), val >> (2 * ZB), tag >> ZB, cnt, cap, err, tc);
     };
     // A lane first marks which of its (vertex, direction) slots hold such an
     // edge, then inserts one marked slot per round: a wave runs as many rounds
@@ -599,10 +676,12 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
         const uint32_t za = zl[p], zb = zl[q];
         const uint64_t ka = lkey<PB>(hk, p), kb = lkey<PB>(hk, q);
         const uint64_t ks = kb < ka ? ka : kb;  // the upper end is the saddle
-        if (tabled)
+        if (tabled) {
             insert((ks << (2 * ZB)) | min(za, zb) | ((uint64_t)max(za, zb) << ZB));
-        else
-            lds_merge<VOL>(TL, hk, mh, za, ks, zb, cnt, cap, err);
+        } else {
+            tc.add(C_TAB_DIRECT);
+            lds_merge<VOL, CNT>(TL, hk, mh, za, ks, zb, cnt, cap, err, tc);
+        }
     }
     __syncthreads();
     // Occupied entries, compacted to the front of the table so that every
@@ -633,7 +712,7 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
     for (uint32_t i = threadIdx.x; i < nw; i += NT) {
         const uint64_t e = htab[i];
         const uint32_t tag = (uint32_t)(e & TAGM);
-        lds_merge<VOL>(TL, hk, mh, tag & (ZMAX - 1), e >> (2 * ZB), tag >> ZB, cnt, cap, err);
+        lds_merge<VOL, CNT>(TL, hk, mh, tag & (ZMAX - 1), e >> (2 * ZB), tag >> ZB, cnt, cap, err, tc);
     }
     __syncthreads();
 
@@ -717,44 +796,59 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
         }
     }
     if (err) atomicOr(&h->status, err);
+    tc.flush(h);
 }
 
 // ---------------------------------------------------------------------------
 // 2. Merge (Alg. 3) across tiles, on the minimum slots
 
+template <bool CNT>
 __device__ void gmerge(Slot *__restrict__ S, const uint64_t *__restrict__ mkey, const float *__restrict__ f,
                        uint32_t flip, uint32_t M, uint32_t n, uint32_t u, uint32_t s, uint64_t ks, uint32_t v,
-                       uint32_t cap, uint32_t &err)
+                       uint32_t cap, uint32_t &err, Tally<CNT> &tc)
 {
-    SlotRead tu = ld_slot(S, u);
-    SlotRead tv = ld_slot(S, v);
-    for (uint32_t step = 0; step < cap; ++step) {
+    tc.add(C_GM_FACTS);
+    SlotRead tu = ld_slot_live(S, u);
+    SlotRead tv = ld_slot_live(S, v);
+    uint32_t step = 0;
+    for (; step < cap; ++step) {
         const uint32_t u1 = hi32(tu.w), su = lo32(tu.w), v1 = hi32(tv.w), sv = lo32(tv.w);
-        if (u1 >= M || v1 >= M || su >= n || sv >= n) { err |= ST_CORRUPT; return; }
-        if (u1 != u && saddle_key(tu, f, flip) < ks) { u = u1; tu = ld_slot(S, u); continue; }
-        if (v1 != v && saddle_key(tv, f, flip) < ks) { v = v1; tv = ld_slot(S, v); continue; }
-        if (u == v) return;
+        if (u1 >= M || v1 >= M || su >= n || sv >= n) { err |= ST_CORRUPT; break; }
+        if (u1 != u && saddle_key(tu, f, flip) < ks) {
+            tc.add(C_GM_DESCENTS);
+            u = u1; tu = ld_slot_live(S, u); continue;
+        }
+        if (v1 != v && saddle_key(tv, f, flip) < ks) {
+            tc.add(C_GM_DESCENTS);
+            v = v1; tv = ld_slot_live(S, v); continue;
+        }
+        if (u == v) break;
         if (mkey[v] < mkey[u]) {  // the upper minimum is re-pointed
             const uint32_t w = u; u = v; v = w;
             const SlotRead tw = tu; tu = tv; tv = tw;
         }
         uint64_t seen = tv.w;
+        tc.add(C_GM_CAS);
         if (__hip_atomic_compare_exchange_strong(&S[v].w, &seen, pack(s, u), __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                                  __HIP_MEMORY_SCOPE_AGENT)) {
             st_relaxed(&S[v].k, ks);
-            if (hi32(tv.w) == v) return;  // v was a root
+            if (hi32(tv.w) == v) break;  // v was a root
+            tc.add(C_GM_REMERGE);
             const uint64_t kv = saddle_key(tv, f, flip);  // merge the displaced triplet again
             s = lo32(tv.w);
             ks = kv;
             v = hi32(tv.w);
-            tv = ld_slot(S, v);
+            tv = ld_slot_live(S, v);
         } else {
+            tc.add(C_GM_CAS_FAIL);
             tv.w = seen;
             tv.k = ld_relaxed(&S[v].k);
         }
-        tu = ld_slot(S, u);
+        tu = ld_slot_live(S, u);
     }
-    err |= ST_LIVELOCK;
+    tc.add(C_GM_STEPS, step + (step < cap));
+    tc.max(C_GM_MAX_STEPS, step + (step < cap));
+    if (step == cap) err |= ST_LIVELOCK;
 }
 
 // Per-workgroup aggregation of bin-counter increments: lanes add into a
@@ -814,7 +908,7 @@ __global__ __launch_bounds__(cross_threads<S>()) void k_cross(const float *__res
                                                  const int64_t *__restrict__ tstart, int nfc, int64_t tile0,
                                                  int64_t ntiles, int remap, uint32_t *__restrict__ qhist,
                                                  const uint64_t *__restrict__ xface, uint32_t flip,
-                                                 Header *__restrict__ h)
+                                                 uint32_t probes, Header *__restrict__ h)
 {
     constexpr int TX = S::TX, TY = S::TY, TZ = S::TZ, NT = cross_threads<S>();
     // faces that can have a neighbour: a 2-D shape has no z face, a 1-D one no y face
@@ -880,7 +974,7 @@ __global__ __launch_bounds__(cross_threads<S>()) void k_cross(const float *__res
         const uint64_t key = (uint64_t)min(za, zb) | ((uint64_t)max(za, zb) << 32);
         uint32_t si = (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> (64 - __builtin_ctz(H)));
         bool placed = false;
-        for (int probe = 0; probe < 32; ++probe) {
+        for (uint32_t probe = 0; probe < probes; ++probe) {
             uint64_t prev = ~0ull;
             __hip_atomic_compare_exchange_strong(hpair + si, &prev, key, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                                  __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -1060,22 +1154,25 @@ __global__ __launch_bounds__(kBlock) void k_qscatter(const Fact *__restrict__ qu
 
 // Merge of the queued cross-tile facts, one per lane; workgroup b serves the
 // queue of XCD b % 8 (the grid is a multiple of 8 workgroups).
+template <bool CNT>
 __global__ __launch_bounds__(kBlock) void k_merge_q(const float *__restrict__ f, const Fact *__restrict__ queue,
                                                     uint32_t qsub, Slot *__restrict__ slot,
                                                     const uint64_t *__restrict__ mkey, uint32_t n, uint32_t cap,
                                                     uint32_t flip, Header *__restrict__ h)
 {
+    Tally<CNT> tc;
     const uint32_t M = h->n_minima;
     const uint32_t x = blockIdx.x % 8, per = gridDim.x / 8;
     const uint32_t Q = min(h->n_cross[x * kXStride], qsub);
     const Fact *__restrict__ mq = queue + (size_t)x * qsub;
     uint32_t err = 0;
-    for (uint32_t i = (blockIdx.x / 8) * kBlock + threadIdx.x; i < Q; i += per * kBlock) {
+    for (int64_t i = (int64_t)(blockIdx.x / 8) * kBlock + threadIdx.x; i < Q; i += (int64_t)per * kBlock) {
         const Fact q = mq[i];
         if (q.a >= M || q.b >= M || lo32(q.ks) >= n) { err |= ST_CORRUPT; continue; }
-        gmerge(slot, mkey, f, flip, M, n, q.a, lo32(q.ks), q.ks, q.b, cap, err);
+        gmerge<CNT>(slot, mkey, f, flip, M, n, q.a, lo32(q.ks), q.ks, q.b, cap, err, tc);
     }
     if (err) atomicOr(&h->status, err);
+    tc.flush(h);
 }
 
 // ---------------------------------------------------------------------------
@@ -1088,7 +1185,7 @@ __device__ __forceinline__ uint32_t chase(Slot *__restrict__ S, const float *__r
                                           uint32_t &err)
 {
     for (uint32_t step = 0; step < cap; ++step) {
-        const SlotRead t = ld_slot(S, x);
+        const SlotRead t = ld_slot_live(S, x);
         const uint32_t v = hi32(t.w), s = lo32(t.w);
         if (v >= M || s >= n) { err |= ST_CORRUPT; return x; }
         if (v == x) return x;
@@ -1104,8 +1201,9 @@ __global__ __launch_bounds__(kBlock) void k_repair_min(const float *__restrict__
 {
     const uint32_t M = h->n_minima;
     uint32_t err = 0;
-    for (uint32_t m = blockIdx.x * kBlock + threadIdx.x; m < M; m += gridDim.x * kBlock) {
-        const SlotRead t = ld_slot(S, m);
+    for (int64_t mm = (int64_t)blockIdx.x * kBlock + threadIdx.x; mm < M; mm += (int64_t)gridDim.x * kBlock) {
+        const uint32_t m = (uint32_t)mm;
+        const SlotRead t = ld_slot_live(S, m);
         const uint32_t v = hi32(t.w), s = lo32(t.w);
         if (v == m) continue;
         if (v >= M || s >= n) { err |= ST_CORRUPT; continue; }
@@ -1122,6 +1220,7 @@ __global__ __launch_bounds__(kBlock) void k_repair_min(const float *__restrict__
 // vertices at once, so the dependent loads of their chases (label -> slot ->
 // slot ... -> minimum key) overlap.
 constexpr int RV = 4;
+template <bool CNT>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_repair_reg(const float *__restrict__ f, const uint32_t *__restrict__ lbl,
                                                        const Slot *__restrict__ S, const uint64_t *__restrict__ mkey,
                                                        uint64_t *__restrict__ T, uint32_t *__restrict__ pcnt,
@@ -1137,6 +1236,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
     const uint32_t off = (uint32_t)d.offset;
     const uint32_t M = h->n_minima;
     uint32_t err = 0, np = 0, nr = 0;
+    Tally<CNT> tc;
     static_assert(kChunk % (kBlock * RV) == 0, "whole groups per chunk");
     for (int64_t g0 = lo; g0 < hi; g0 += kBlock * RV) {
         uint32_t u[RV], z[RV], x[RV], s[RV], gr[RV];
@@ -1194,6 +1294,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
         }
         for (uint32_t step = 0; act != 0; ++step) {
             if (step == cap) { err |= ST_LIVELOCK; break; }
+            tc.add(C_REG_CHASES, (uint32_t)__builtin_popcount(act));
             // all RV loads issued together, no branch around them: a vertex
             // whose chase has ended reads slot 0 (one shared line per wave)
 #pragma unroll
@@ -1241,6 +1342,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
         if (b) atomicAdd((unsigned long long *)&h->roots, (unsigned long long)b);
     }
     if (err) atomicOr(&h->status, err);
+    tc.flush(h);
 }
 
 // ---------------------------------------------------------------------------
@@ -1468,7 +1570,8 @@ __global__ __launch_bounds__(kBlock) void k_rank_keys(const float *__restrict__ 
                                                       uint64_t *__restrict__ keys, Header *__restrict__ h)
 {
     bool nan = false;
-    for (uint32_t u = blockIdx.x * kBlock + threadIdx.x; u < n; u += gridDim.x * kBlock) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        const uint32_t u = (uint32_t)i;
         const float x = f[u];
         nan |= x != x;
         keys[u] = vkey(f, u, flip);
@@ -1479,9 +1582,9 @@ __global__ __launch_bounds__(kBlock) void k_rank_keys(const float *__restrict__ 
 __global__ __launch_bounds__(kBlock) void k_rank_scatter(const uint64_t *__restrict__ sorted, uint32_t n,
                                                          uint32_t *__restrict__ rank)
 {
-    for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
         const uint32_t u = lo32(sorted[i]);
-        if (u < n) rank[u] = i;
+        if (u < n) rank[u] = (uint32_t)i;
     }
 }
 

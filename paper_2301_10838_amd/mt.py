@@ -33,6 +33,14 @@ EXPORTS = [
     "mt_profile_end", "mt_profile_count", "mt_profile_get", "mt_tile_shape_count", "mt_tile_shape_info",
     "mt_set_tile_shape", "mt_get_tile_shape", "mt_autotune_workspace_bytes", "mt_autotune", "mt_build_tree",
     "mt_batch_build_tree", "mt_build_pairs", "mt_vertex_ranks", "mt_rank_workspace_bytes",
+    "mt_set_max_steps", "mt_get_max_steps", "mt_set_table_probes", "mt_get_table_probes", "mt_workspace_reset",
+    "mt_set_counting", "mt_get_counting", "mt_read_counters",
+]
+
+COUNTER_NAMES = [
+    "gm_facts", "gm_steps", "gm_descents", "gm_cas", "gm_cas_fail", "gm_remerge", "gm_max_steps",
+    "lds_merges", "lds_steps", "lds_cas", "lds_cas_fail", "lds_max_steps",
+    "table_inserts", "table_probes", "table_direct", "output_chase_steps",
 ]
 
 # tree kinds (include/mt.h)
@@ -116,6 +124,22 @@ def load_library():
     lib.mt_autotune_workspace_bytes.restype = SZ
     lib.mt_autotune.argtypes = [P, P, I32, P, P, P, SZ, ctypes.c_int, P, P]
     lib.mt_autotune.restype = ctypes.c_int
+    lib.mt_set_max_steps.argtypes = [I64]
+    lib.mt_set_max_steps.restype = ctypes.c_int
+    lib.mt_get_max_steps.argtypes = []
+    lib.mt_get_max_steps.restype = I64
+    lib.mt_set_table_probes.argtypes = [ctypes.c_int]
+    lib.mt_set_table_probes.restype = ctypes.c_int
+    lib.mt_get_table_probes.argtypes = []
+    lib.mt_get_table_probes.restype = ctypes.c_int
+    lib.mt_workspace_reset.argtypes = [P, SZ, P]
+    lib.mt_workspace_reset.restype = ctypes.c_int
+    lib.mt_set_counting.argtypes = [ctypes.c_int]
+    lib.mt_set_counting.restype = ctypes.c_int
+    lib.mt_get_counting.argtypes = []
+    lib.mt_get_counting.restype = ctypes.c_int
+    lib.mt_read_counters.argtypes = [P, P, P, ctypes.c_int]
+    lib.mt_read_counters.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -155,14 +179,29 @@ def workspace_bytes(shape) -> int:
 
 
 def alloc_workspace(nbytes: int, device) -> torch.Tensor:
-    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+    """Device workspace of at least `nbytes` bytes with its status head
+    cleared (mt_workspace_reset), so that no leftover byte reads as an error."""
+    ws = torch.empty(max(int(nbytes), 4096), dtype=torch.uint8, device=device)
+    workspace_reset(ws)
+    return ws
+
+
+def workspace_reset(workspace: torch.Tensor):
+    _check(load_library().mt_workspace_reset(workspace.data_ptr(), workspace.numel() * workspace.element_size(),
+                                             _stream_ptr(workspace.device)), "mt_workspace_reset")
 
 
 def mt_build(field: torch.Tensor, triplets: torch.Tensor | None = None,
-             workspace: torch.Tensor | None = None, kind="merge") -> torch.Tensor:
+             workspace: torch.Tensor | None = None, kind="merge", check: bool = True) -> torch.Tensor:
     """Triplets T[u] = (s, v) of the merge tree (kind "merge") or split tree
     (kind "split": the merge tree of -f) of `field` (int32 [N, 2], uint32 bit
-    patterns)."""
+    patterns).
+
+    The C call is asynchronous and latches device-side errors (a NaN in the
+    field, a loop that hit the step cap) in the workspace.  With check=True
+    (the default) this waits for the build and raises MTError on such a
+    status; with check=False it returns at once and the status is read later
+    (sync_status, or mt_persistence_pairs on the same workspace)."""
     lib = load_library()
     f = _field(field)
     nx, ny, nz = grid_dims(f.shape)
@@ -174,6 +213,8 @@ def mt_build(field: torch.Tensor, triplets: torch.Tensor | None = None,
     rc = lib.mt_build_tree(f.data_ptr(), nx, ny, nz, _kind(kind), triplets.data_ptr(), workspace.data_ptr(),
                            workspace.numel(), _stream_ptr(f.device))
     _check(rc, "mt_build_tree")
+    if check:
+        sync_status(workspace)
     return triplets
 
 
@@ -460,3 +501,36 @@ def autotune(fields: Sequence[torch.Tensor], reps: int = 3):
 
 def release_caches():
     load_library().mt_release_caches()
+
+
+def set_max_steps(steps: int):
+    """Step cap of every merge/descent/chase loop (0 restores the default)."""
+    _check(load_library().mt_set_max_steps(int(steps)), "mt_set_max_steps")
+
+
+def get_max_steps() -> int:
+    return int(load_library().mt_get_max_steps())
+
+
+def set_table_probes(probes: int):
+    """Probes per edge in the LDS pair tables before the table-free path (-1 restores the default)."""
+    _check(load_library().mt_set_table_probes(int(probes)), "mt_set_table_probes")
+
+
+def get_table_probes() -> int:
+    return int(load_library().mt_get_table_probes())
+
+
+def set_counting(on: bool):
+    """Counting build on (event counters in the workspace) or off (the timed kernels)."""
+    _check(load_library().mt_set_counting(1 if on else 0), "mt_set_counting")
+
+
+def read_counters(workspace: torch.Tensor) -> dict:
+    """Event counters of the last counting build on `workspace` (synchronizes)."""
+    n = len(COUNTER_NAMES)
+    buf = (ctypes.c_uint64 * n)()
+    rc = load_library().mt_read_counters(workspace.data_ptr(), _stream_ptr(workspace.device), buf, n)
+    if rc < 0:
+        raise MTError(rc, "mt_read_counters")
+    return {COUNTER_NAMES[i]: int(buf[i]) for i in range(n)}

@@ -112,6 +112,24 @@ def test_host_argument_checks(lib):
     assert lib.mt_sync_status(None, None, None, None) == -6
 
 
+def test_setter_bounds(lib):
+    """Loop bounds: out-of-range settings are refused on the host; the
+    defaults are restored by 0 / -1.  (No GPU work is enqueued.)"""
+    assert lib.mt_get_max_steps() == 1 << 24
+    assert lib.mt_set_max_steps(-1) == -1
+    assert lib.mt_set_max_steps(1 << 31) == -1
+    assert lib.mt_set_max_steps(5) == 0 and lib.mt_get_max_steps() == 5
+    assert lib.mt_set_max_steps(0) == 0 and lib.mt_get_max_steps() == 1 << 24
+    assert lib.mt_get_table_probes() == 32
+    assert lib.mt_set_table_probes(-2) == -1
+    assert lib.mt_set_table_probes(65) == -1
+    assert lib.mt_set_table_probes(0) == 0 and lib.mt_get_table_probes() == 0
+    assert lib.mt_set_table_probes(-1) == 0 and lib.mt_get_table_probes() == 32
+    assert lib.mt_workspace_reset(None, 4096, None) == -6
+    assert lib.mt_workspace_reset(ctypes.c_void_p(0x10010), 4096, None) == -6
+    assert lib.mt_workspace_reset(ctypes.c_void_p(0x10000), 64, None) == -6
+
+
 def test_binding_refuses_cpu_tensors():
     import torch
 

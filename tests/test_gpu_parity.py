@@ -175,10 +175,22 @@ def test_nan_reported(dev):
     f[3, 4, 5] = np.nan
     ft = torch.from_numpy(f).to(dev)
     ws = mt.alloc_workspace(mt.workspace_bytes(f.shape), dev)
-    T = mt.mt_build(ft, workspace=ws)
+    # checked build: the binding reads the latched status and raises
+    with pytest.raises(mt.MTError) as e:
+        mt.mt_build(ft, workspace=ws)
+    assert e.value.status == -3
+    # unchecked build: the status stays latched for the pairs call on the same workspace
+    T = mt.mt_build(ft, workspace=ws, check=False)
     with pytest.raises(mt.MTError) as e:
         mt.mt_persistence_pairs(ft, T, workspace=ws)
     assert e.value.status == -3
+    # a workspace the build did not use starts clean (the binding resets it)
+    ws2 = mt.alloc_workspace(mt.workspace_bytes(f.shape), dev)
+    g = torch.from_numpy(fields.uniform((20, 20, 20), 5)).to(dev)
+    T2 = mt.mt_build(g, workspace=ws2)
+    ws3 = torch.full_like(ws2, 0xFF)  # every status bit set
+    mt.workspace_reset(ws3)
+    mt.mt_persistence_pairs(g, T2, workspace=ws3)
 
 
 def test_capacity_reported(dev):
