@@ -5,10 +5,16 @@ One step = the whole single-field hot path on the 512^3 log-normal k^-3 field
 synchronizes to return the pair count), with the field already resident in
 HBM.  Prints one JSON line.
 
+The timed loop runs with no event bracketing; per-kernel times come from a
+separate pass with the library's HIP-event timing on.
+
 Also reported (under "secondary"): the uneven 48-field batch in one graph
-launch against 48 plain calls, the backward scatter of a 16 x 128^3
-differentiable batch, the split tree of the timed field, and the global sort
-a rank-keyed build would start with (mt_vertex_ranks) set against the step.
+launch against 48 plain calls (synchronous, and as 48 asynchronous
+single-field graph launches), the same batch with autotuned tile shapes, the
+backward scatter of a 16 x 128^3 differentiable batch over 100 gradient
+steps, the split tree of the timed field, adversarial fields, and the global
+sort a rank-keyed build would start with (mt_vertex_ranks) set against the
+step.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
@@ -33,11 +39,24 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
 SRCS = [os.path.join(ROOT, "paper_2301_10838_amd", "csrc", n) for n in ("mt.hip", "mt_device.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
-# Compulsory HBM bytes each kernel must move, per vertex of its launch (plus
-# the per-minimum and per-pair terms noted in algo_bytes).  "Minima" here are
-# the local minima of the tiles, whose 24-byte records (16-byte slot + 8-byte
-# key) the kernels pass on to each other.
-ALGO_BYTES_PER_VERTEX = {
+# Compulsory HBM bytes of the whole path: read the field (4 B) and write the
+# triplet (8 B) of every vertex, write every pair (two 4-byte ids, two
+# 4-byte values).  Nothing else has to cross HBM.
+COMPULSORY_PER_VERTEX = 12
+COMPULSORY_PER_PAIR = 16
+
+
+def compulsory_bytes(n_vertices: int, n_pairs: int) -> float:
+    return float(COMPULSORY_PER_VERTEX * n_vertices + COMPULSORY_PER_PAIR * n_pairs)
+
+
+# The kernels' own byte model: what each kernel must move given the
+# intermediate records this design passes between kernels (labels, minimum
+# slots, queued facts).  It is a model of this implementation, reported as
+# such, not the algorithm's compulsory traffic above.  "Minima" are the local
+# minima of the tiles, whose 24-byte records (16-byte slot + 8-byte key) the
+# kernels pass on to each other.
+MODEL_BYTES_PER_VERTEX = {
     "k_local": 8,        # read f, write the local-basin label
     "k_cross": 0,        # per-face-edge and per-fact terms below
     "k_qscatter": 0,     # per-fact term below
@@ -49,9 +68,9 @@ ALGO_BYTES_PER_VERTEX = {
 }
 
 
-def algo_bytes(kernel: str, n_vertices: int, n_pairs: int, n_local_minima: int, n_facts: int = 0,
-               n_face_edges: int = 0) -> float:
-    b = ALGO_BYTES_PER_VERTEX[kernel] * n_vertices
+def model_bytes(kernel: str, n_vertices: int, n_pairs: int, n_local_minima: int, n_facts: int = 0,
+                n_face_edges: int = 0) -> float:
+    b = MODEL_BYTES_PER_VERTEX[kernel] * n_vertices
     if kernel == "k_qscatter":
         b += 32 * n_facts          # every fact read from the queue and written to its bin
     if kernel == "k_merge_q":
@@ -87,9 +106,10 @@ def src_hash() -> str:
     return h.hexdigest()
 
 
-def stored_traffic(kernel: str, workload: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source."""
+def stored_traffic(workload: str):
+    """HBM bytes per launch of every kernel, {name: bytes}, from the committed
+    rocprofv3 counter summary, if it was taken on the current kernel source
+    and workload; else None."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
@@ -97,10 +117,7 @@ def stored_traffic(kernel: str, workload: str):
         return None
     if t.get("src_sha256") != src_hash() or t.get("workload") != workload:
         return None
-    k = t.get("kernels", {}).get(kernel)
-    if not k:
-        return None
-    return float(k["fetch_bytes"] + k["write_bytes"])
+    return {k: float(v["fetch_bytes"] + v["write_bytes"]) for k, v in t.get("kernels", {}).items()}
 
 
 class Single:
@@ -147,59 +164,86 @@ class Single:
         return self.mt.build_stats(self.ws)
 
 
-def cpu_baseline(f: np.ndarray, dev, mt, lib):
-    """Oracle (serial, one core) on a bounded slab of the workload, and the GPU
-    on the same slab, checked bit for bit."""
-    import torch
+def cpu_info():
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model
 
+
+def cpu_baseline(f: np.ndarray, T_gpu: np.ndarray, birth_gpu: np.ndarray, death_gpu: np.ndarray):
+    """The oracle (serial sort + union-find sweep + pairs, one core) on the
+    whole timed field, once; the GPU's triplets and pairs of the same field
+    are checked against it bit for bit.  A z < 64 slab is timed beside it."""
     import oracle
 
-    nz = f.shape[0]
-    slab_z = 64 if f.ndim == 3 and nz > 64 else nz
-    sample = np.ascontiguousarray(f[:slab_z])
     t0 = time.perf_counter()
-    T_ref = oracle.merge_tree(sample)
-    rb, rd, _, _, _ = oracle.pairs(sample, T_ref)
+    T_ref = oracle.merge_tree(f)
+    rb, rd, _, _, _ = oracle.pairs(f, T_ref)
     dt = time.perf_counter() - t0
-    s = Single(torch.from_numpy(sample).to(dev), lib, mt)
-    P, _ = s.step()
-    torch.cuda.synchronize()
-    exact = bool(np.array_equal(s.T.cpu().numpy().view(np.uint32), T_ref)
-                 and np.array_equal(s.b[:P].cpu().numpy().view(np.uint32), rb)
-                 and np.array_equal(s.d[:P].cpu().numpy().view(np.uint32), rd))
+    exact = bool(np.array_equal(T_gpu, T_ref) and np.array_equal(birth_gpu, rb) and np.array_equal(death_gpu, rd))
+    del T_ref
+    slab = {}
+    if f.ndim == 3 and f.shape[0] > 64:
+        sample = np.ascontiguousarray(f[:64])
+        t1 = time.perf_counter()
+        Ts = oracle.merge_tree(sample)
+        oracle.pairs(sample, Ts)
+        ds = time.perf_counter() - t1
+        slab = {"slab": f"z < 64, {list(sample.shape)}", "slab_s": ds, "slab_Mvertices_per_s": sample.size / ds / 1e6}
     return {
-        "value": sample.size / dt / 1e6,
+        "value": f.size / dt / 1e6,
         "unit": "Mvertices/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": f"z < {slab_z} slab {list(sample.shape)} ({sample.size} vertices) of the timed field; "
-                  f"serial sort + union-find sweep + pairs, {dt:.1f} s",
+        "sample": f"the whole timed field {list(f.shape)} ({f.size} vertices), one run of {dt:.1f} s: serial "
+                  f"sort + union-find sweep + pairs (gcc -O2, one thread)",
+        "seconds": dt,
         "host_cores_available": os.cpu_count(),
+        "host_cpu": cpu_info(),
         "gpu_bit_exact_on_sample": exact,
+        **slab,
     }
 
 
 def bench_batch(dev, mt, lib, reps: int = 5):
+    """The uneven 48-field batch: one graph launch against per-field calls,
+    both the synchronous fused call (mt_build_pairs, which waits for its pair
+    count) and one asynchronous single-field graph launch per field with one
+    wait at the end; then the batch again with tile shapes picked by the
+    autotuner."""
     import torch
 
-    from paper_2301_10838_amd import fields
+    from paper_2301_10838_amd import fields, tune
 
     fs = fields.workload("batch48")
     shapes = [f.shape for f in fs]
     plan = mt.BatchPlan(shapes, dev)
     plan.load([torch.from_numpy(f).to(dev) for f in fs])
     n_total = plan.n_total
-    for _ in range(2):
-        plan.launch()
-        plan.sync_status()
-    torch.cuda.synchronize()
-    tb = []
-    for _ in range(reps):
-        t0 = time.perf_counter()
-        plan.launch()
-        P = plan.sync_status()
-        tb.append(time.perf_counter() - t0)
-    # plain: one mt_build_pairs call per field
+
+    def time_batch(pl):
+        for _ in range(2):
+            pl.launch()
+            pl.sync_status()
+        torch.cuda.synchronize()
+        tb = []
+        P = 0
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            pl.launch()
+            P = pl.sync_status()
+            tb.append(time.perf_counter() - t0)
+        return statistics.median(tb), P
+
+    tb_med, P = time_batch(plan)
+    # plain, synchronous: one mt_build_pairs call per field
     singles = [Single(plan.fields[plan.vertex_offsets[i]:plan.vertex_offsets[i + 1]].view(shapes[i]), lib, mt)
                for i in range(len(shapes))]
     for s in singles:
@@ -212,6 +256,25 @@ def bench_batch(dev, mt, lib, reps: int = 5):
             s.step()
         torch.cuda.synchronize()
         tp.append(time.perf_counter() - t0)
+    # plain, asynchronous: one single-field graph launch per field, one wait
+    aplans = []
+    for i, shp in enumerate(shapes):
+        ap = mt.BatchPlan([shp], dev)
+        ap.load([plan.fields[plan.vertex_offsets[i]:plan.vertex_offsets[i + 1]]])
+        aplans.append(ap)
+    for ap in aplans:
+        ap.launch()
+    for ap in aplans:
+        ap.sync_status()
+    ta = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        for ap in aplans:
+            ap.launch()
+        torch.cuda.synchronize()
+        ta.append(time.perf_counter() - t0)
+    for ap in aplans:
+        ap.sync_status()
     # identical results, field by field
     offs = plan.pair_offsets.cpu().numpy()
     T_all = plan.triplets.cpu().numpy().view(np.uint32)
@@ -221,21 +284,84 @@ def bench_batch(dev, mt, lib, reps: int = 5):
         a, b = plan.vertex_offsets[i], plan.vertex_offsets[i + 1]
         p = s.np.value
         same &= bool(np.array_equal(T_all[a:b], s.T.cpu().numpy().view(np.uint32)))
+        same &= bool(np.array_equal(T_all[a:b], aplans[i].triplets.cpu().numpy().view(np.uint32)))
         same &= bool(offs[i + 1] - offs[i] == p)
         same &= bool(np.array_equal(b_all[offs[i]:offs[i + 1]], s.b[:p].cpu().numpy().view(np.uint32)))
-    tb_med, tp_med = statistics.median(tb), statistics.median(tp)
-    return {
+    del singles, aplans
+    tp_med, ta_med = statistics.median(tp), statistics.median(ta)
+    out = {
         "workload": "batch48",
         "fields": len(shapes),
         "vertices": n_total,
         "pairs": int(P),
         "batched_ms": tb_med * 1e3,
         "plain_ms": tp_med * 1e3,
+        "plain_async_ms": ta_med * 1e3,
         "batched_Mvertices_per_s": n_total / tb_med / 1e6,
         "plain_Mvertices_per_s": n_total / tp_med / 1e6,
         "batched_over_plain": tp_med / tb_med,
+        "batched_over_plain_async": ta_med / tb_med,
         "batched_equals_plain": same,
     }
+    # autotuned tile shapes (timed by the library, bit-identity checked on
+    # the device), then the batch again with them; defaults restored after
+    saved = [mt.get_tile_shape(c) for c in range(3)]
+    saved_cache = os.environ.get("MT_AUTOTUNE_CACHE")
+    os.environ["MT_AUTOTUNE_CACHE"] = os.path.join("/tmp", f"mt_autotune_bench_{os.getpid()}.json")
+    try:
+        tensors = [plan.fields[plan.vertex_offsets[i]:plan.vertex_offsets[i + 1]].view(shapes[i])
+                   for i in range(len(shapes))]
+        chosen = tune.tune(tensors, reps=3, force=True)
+        tplan = mt.BatchPlan(shapes, dev)
+        tplan.fields.copy_(plan.fields)
+        tt_med, _ = time_batch(tplan)
+        same_t = bool(torch.equal(tplan.triplets, plan.triplets))
+        info = {s["id"]: s for s in mt.tile_shapes()}
+        out["tuned"] = {"shapes": {k: [info[v]["tx"], info[v]["ty"], info[v]["tz"]] for k, v in chosen.items()},
+                        "default_shapes": {tune.CLASS_NAMES[c]: [info[saved[c]]["tx"], info[saved[c]]["ty"],
+                                                                 info[saved[c]]["tz"]] for c in range(3)},
+                        "batched_ms": tt_med * 1e3, "over_default": tb_med / tt_med, "equals_default": same_t}
+        del tplan
+    finally:
+        for c in range(3):
+            mt.set_tile_shape(c, saved[c])
+        if saved_cache is None:
+            os.environ.pop("MT_AUTOTUNE_CACHE", None)
+        else:
+            os.environ["MT_AUTOTUNE_CACHE"] = saved_cache
+    return out
+
+
+def bench_adversarial(dev, mt, lib, side: int = 256, steps: int = 3):
+    """Build + pairs time of the adversarial fields at side^3 against the
+    log-normal field of the same size."""
+    import torch
+
+    from paper_2301_10838_amd import fields
+
+    cases = [
+        ("lognormal_grf", lambda: fields.lognormal_grf((side,) * 3, 41)),
+        ("serpentine", lambda: fields.serpentine((side,) * 3, 42)),
+        ("tilted_checkerboard", lambda: fields.tilted_checkerboard((side,) * 3, 43)),
+        ("parity_lattice", lambda: fields.parity_lattice((side,) * 3)),
+        ("plateau_jump", lambda: fields.plateau_jump((side,) * 3, 44)),
+        ("plateau_jump_noise", lambda: fields.plateau_jump((side,) * 3, 45, noise=1e-6)),
+        ("nested_plateaus", lambda: fields.nested_plateaus((side,) * 3, 46)),
+    ]
+    out = {}
+    for name, maker in cases:
+        f = maker()
+        s = Single(torch.from_numpy(f).to(dev), lib, mt)
+        s.step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            P, _ = s.step()
+        dt = (time.perf_counter() - t0) / steps
+        out[name] = {"ms": dt * 1e3, "Mvertices_per_s": s.N / dt / 1e6, "pairs": P}
+        del s
+    worst = max(out, key=lambda k: out[k]["ms"])
+    return {"shape": [side] * 3, "cases": out, "worst": worst}
 
 
 def bench_split(ft, lib, mt, s, steps: int = 5):
@@ -299,7 +425,12 @@ def bench_ranks(ft, lib, mt, step_ms: float, steps: int = 5):
             "over_value_keyed_step": dt * 1e3 / step_ms}
 
 
-def bench_backward(dev, mt, steps: int = 20):
+def bench_backward(dev, mt, steps: int = 100):
+    """Gradient descent on the topological simplification loss
+    sum over pairs with d - b < 0.05 of (d - b)^2, 16 bump fields at 128^3.
+    bwd = loss.backward() (the loss's own backward ops, the autograd function
+    and the adjoint kernels), timed with events; the adjoint kernels alone
+    with the library's event timing."""
     import torch
 
     from paper_2301_10838_amd import fields
@@ -308,7 +439,7 @@ def bench_backward(dev, mt, steps: int = 20):
     plan = mt.BatchPlan([f.shape for f in fs], dev)
     flat = torch.cat([torch.from_numpy(f).to(dev).reshape(-1) for f in fs])
     tau, lr = 0.05, 0.1
-    bwd_us, fwd_ms, losses = [], [], []
+    bwd_us, fwd_ms, host_bwd_us, losses, pairs = [], [], [], [], []
     mt.profile_begin()
     for it in range(steps):
         x = flat.clone().requires_grad_(True)
@@ -318,22 +449,36 @@ def bench_backward(dev, mt, steps: int = 20):
         pers = deaths - births
         loss = torch.where(pers < tau, pers * pers, torch.zeros_like(pers)).sum()
         e1.record()
+        h0 = time.perf_counter()
         loss.backward()
         e2.record()
         torch.cuda.synchronize()
+        host_bwd_us.append((time.perf_counter() - h0) * 1e6)
         fwd_ms.append(e0.elapsed_time(e1))
         bwd_us.append(e1.elapsed_time(e2) * 1e3)
-        losses.append(float(loss))
+        losses.append(float(loss.detach()))
+        pairs.append(births.numel())
         with torch.no_grad():
             flat -= lr * x.grad
     ks = mt.profile_end()
-    kern_ms = sum(ks.get(k, (0.0, 0))[0] for k in ("k_fill0", "k_scatter"))
+    kern = {k: ks[k] for k in ("k_fill0", "k_scatter") if k in ks}
+    kern_us = sum(v[0] for v in kern.values()) / steps * 1e3
+    P = statistics.median(pairs)
+    # compulsory bytes of the adjoint: zero every gradient entry (4 B/vertex),
+    # read each pair's two ids and two upstream gradients (16 B), read and
+    # write the two gradient entries it lands on (16 B)
+    adj_bytes = 4 * plan.n_total + 32 * P
     return {
         "workload": "diff16x128",
         "vertices": plan.n_total,
         "steps": steps,
-        "bwd_kernel_us": kern_ms / steps * 1e3,
+        "pairs_median": P,
         "bwd_us_median": statistics.median(bwd_us[2:]),
+        "bwd_host_us_median": statistics.median(host_bwd_us[2:]),
+        "bwd_kernel_us": kern_us,
+        "bwd_kernels": {k: {"avg_us": v[0] / v[1] * 1e3, "launches": v[1]} for k, v in kern.items()},
+        "adjoint_roofline": {"bound": "hbm", "bytes": adj_bytes, "achieved_GBps": adj_bytes / (kern_us * 1e3),
+                             "frac": adj_bytes / (kern_us * 1e3) / HBM_PEAK_GBS},
         "fwd_ms_median": statistics.median(fwd_ms[2:]),
         "loss_first": losses[0],
         "loss_last": losses[-1],
@@ -444,37 +589,65 @@ def main():
         s.step()
     torch.cuda.synchronize()
 
-    mt.profile_begin()
+    # timed region: K whole steps, nothing else on the stream
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         P, R = s.step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    kstats = mt.profile_end()
     dt = (t1 - t0) / args.steps
     N = s.N
 
+    # per-kernel times in a separate pass (HIP events around every launch)
+    mt.profile_begin()
+    for _ in range(args.steps):
+        s.step()
+    torch.cuda.synchronize()
+    kstats = mt.profile_end()
+
     n_min, n_facts = s.build_stats()  # local minima records and queued cross-tile facts (untimed)
+    s.step()
+    torch.cuda.synchronize()
     n_face = face_edges(f.shape, mt)
-    dom = max((k for k in kstats if k in ALGO_BYTES_PER_VERTEX), key=lambda k: kstats[k][0])
+    per_kernel = {k: {"avg_ms": v[0] / v[1], "launches": v[1]} for k, v in sorted(kstats.items())}
+    kernel_ms_sum = sum(v[0] for v in kstats.values()) / args.steps
+    traffic = stored_traffic(args.workload)
+
+    # roofline of the dominant kernel: the path's per-vertex compulsory bytes
+    # (read f, write T: 12 B) times the vertices one launch sweeps
+    dom = max((k for k in kstats if k in MODEL_BYTES_PER_VERTEX), key=lambda k: kstats[k][0])
     avg_s = kstats[dom][0] / kstats[dom][1] / 1e3
-    ab = algo_bytes(dom, N, P, n_min, n_facts, n_face)
+    ab = float(COMPULSORY_PER_VERTEX * N)
     achieved = ab / avg_s / 1e9
-    traffic = stored_traffic(dom, args.workload)
     roofline = {
         "bound": "hbm",
         "achieved": achieved,
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": achieved / HBM_PEAK_GBS,
-        "traffic": traffic,
+        "traffic": traffic.get(dom) if traffic else None,
         "kernel": dom,
         "kernel_avg_ms": avg_s * 1e3,
         "algo_bytes_per_launch": ab,
+        "algo_bytes_rule": "12 B per vertex of the launch (read f, write T)",
     }
-    per_kernel = {k: {"avg_ms": v[0] / v[1], "launches": v[1]} for k, v in sorted(kstats.items())}
-    path_bytes = sum(algo_bytes(k, N, P, n_min, n_facts, n_face) for k in ALGO_BYTES_PER_VERTEX)
+    cb = compulsory_bytes(N, P)
+    path = {
+        "compulsory_bytes": cb,
+        "compulsory_frac": cb / dt / 1e9 / HBM_PEAK_GBS,
+        "kernel_ms_sum": kernel_ms_sum,
+        "counter_bytes": None,
+        "counter_frac_step": None,
+        "counter_frac_kernels": None,
+    }
+    if traffic:
+        ctot = sum(traffic.get(k, 0.0) for k in kstats)
+        path.update(counter_bytes=ctot, counter_frac_step=ctot / dt / 1e9 / HBM_PEAK_GBS,
+                    counter_frac_kernels=ctot / (kernel_ms_sum * 1e6) / HBM_PEAK_GBS)
+    model = {k: {"bytes": model_bytes(k, N, P, n_min, n_facts, n_face),
+                 "GBps": model_bytes(k, N, P, n_min, n_facts, n_face) / (kstats[k][0] / kstats[k][1] * 1e6)}
+             for k in kstats if k in MODEL_BYTES_PER_VERTEX}
 
     out = {
         "metric": "Mvertices/s merge tree+pairs (bit-exact), batched vs plain; %HBM peak; bwd μs",
@@ -493,8 +666,9 @@ def main():
                    "pairs": P, "roots": R, "tile_local_minima": n_min,
                    "cross_tile_facts": n_facts, "tile_face_edges": n_face},
         "roofline": roofline,
-        "path_algo_GBps": path_bytes / dt / 1e9,
+        "path": path,
         "kernels": per_kernel,
+        "model_bytes": model,
     }
     if args.calibrate_copy:
         src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
@@ -504,12 +678,21 @@ def main():
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = {"read": src.numel() * 4, "write": dst.numel() * 4}
         del src, dst
+    T_host = s.T.cpu().numpy().view(np.uint32).reshape(-1, 2)
+    b_host = s.b[:P].cpu().numpy().view(np.uint32)
+    d_host = s.d[:P].cpu().numpy().view(np.uint32)
     if not args.no_secondary:
-        out["secondary"] = {"batched": bench_batch(dev, mt, lib), "backward": bench_backward(dev, mt),
-                            "split_tree": bench_split(ft, lib, mt, s),
-                            "rank_keys": bench_ranks(ft, lib, mt, dt * 1e3)}
+        sec = {}
+        sec["split_tree"] = bench_split(ft, lib, mt, s)
+        sec["rank_keys"] = bench_ranks(ft, lib, mt, dt * 1e3)
+        del s
+        torch.cuda.empty_cache()
+        sec["batched"] = bench_batch(dev, mt, lib)
+        sec["backward"] = bench_backward(dev, mt)
+        sec["adversarial"] = bench_adversarial(dev, mt, lib)
+        out["secondary"] = sec
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(f, dev, mt, lib)
+        out["cpu_baseline"] = cpu_baseline(f, T_host, b_host, d_host)
     print(json.dumps(out), flush=True)
 
 

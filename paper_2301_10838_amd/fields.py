@@ -113,6 +113,121 @@ def lognormal_grf(shape, seed: int, slope: float = -3.0) -> np.ndarray:
     return np.exp(g).astype(np.float32)
 
 
+# Adversarial structure ------------------------------------------------------
+#
+# Fields built to stress the parts of the build that the smooth workloads
+# barely touch: deep chains across many tiles, the largest possible number of
+# minima, large exact-tie plateaus next to noise (the sudden jump in sublevel
+# volume and the suspected quadratic worst case the paper discusses for the
+# Richtmyer-Meshkov data, Sec. 4), and nested plateaus.
+
+def serpentine(shape, seed: int, descending: bool = False) -> np.ndarray:
+    """One monotone path that snakes through the whole grid; every other
+    vertex is higher than the whole path.
+
+    3-D: the path runs along x in every row (y, z) with y and z even,
+    alternating direction, steps to the next row through the vertex between
+    them at the row's end, and to the next even z layer through the vertex
+    above the layer's last row end.  Path vertex k (k-th along the path) gets
+    value k (or its reverse with ``descending``); the rest get N + U[0, N),
+    rounded to float32.  2-D uses the rows y even; 1-D is the whole line.
+    """
+    shape = tuple(int(s) for s in shape)
+    rng = _rng(seed)
+    n = int(np.prod(shape))
+    f = (n + rng.random(n) * n).reshape(shape)
+    if len(shape) == 1:
+        order = np.arange(shape[0])
+        coords = [order]
+    else:
+        nz = shape[0] if len(shape) == 3 else 1
+        ny, nx = shape[-2], shape[-1]
+        pts = []  # (z, y, x) along the path
+        flip = False
+        yrows = list(range(0, ny, 2))
+        for zi, z in enumerate(range(0, nz, 2)):
+            rows = yrows if zi % 2 == 0 else yrows[::-1]
+            for ri, y in enumerate(rows):
+                xs = range(nx - 1, -1, -1) if flip else range(nx)
+                pts.extend((z, y, x) for x in xs)
+                x_end = 0 if flip else nx - 1
+                flip = not flip
+                if ri + 1 < len(rows):  # through the vertex between this row and the next
+                    ym = (y + rows[ri + 1]) // 2
+                    pts.append((z, ym, x_end))
+            if z + 2 < nz:  # up through the vertex above the layer's last point
+                zl, yl, xl = pts[-1]
+                pts.append((z + 1, yl, xl))
+        p = np.array(pts)
+        coords = [p[:, 0], p[:, 1], p[:, 2]] if len(shape) == 3 else [p[:, 1], p[:, 2]]
+    k = np.arange(len(coords[0]), dtype=np.float64)
+    if descending:
+        k = k[::-1].copy()
+    f[tuple(coords)] = k
+    return f.astype(np.float32)
+
+
+def tilted_checkerboard(shape, seed: int, tilt: float = 1e-3) -> np.ndarray:
+    """Parity checkerboard (every even vertex a minimum: the most minima a grid
+    graph can have) on a linear ramp along the linear id, plus a little noise,
+    so that minima are ordered and elder-rule chains are long."""
+    shape = tuple(int(s) for s in shape)
+    idx = np.indices(shape)
+    par = (idx.sum(axis=0) % 2).astype(np.float64)
+    n = int(np.prod(shape))
+    ramp = np.arange(n, dtype=np.float64).reshape(shape) / n
+    noise = _rng(seed).random(shape) * tilt * 0.01
+    return (par + tilt * ramp + noise).astype(np.float32)
+
+
+def plateau_jump(shape, seed: int, noise: float = 0.0) -> np.ndarray:
+    """Half of the domain (z below the middle) on one exact plateau at 0.5, the
+    other half i.i.d. uniform [0, 1) on a coarse grid of 2^-12 steps (many
+    ties), so that at level 0.5 the sublevel set jumps by half the volume.
+    ``noise`` > 0 adds that much uniform noise to the plateau (values then
+    almost, but not exactly, equal)."""
+    shape = tuple(int(s) for s in shape)
+    rng = _rng(seed)
+    f = np.floor(rng.random(shape) * 4096.0) / 4096.0
+    half = shape[0] // 2
+    pl = np.full((half,) + shape[1:], 0.5)
+    if noise > 0:
+        pl = pl + noise * rng.random(pl.shape)
+    f[:half] = pl
+    return f.astype(np.float32)
+
+
+def nested_plateaus(shape, seed: int, width: int = 6) -> np.ndarray:
+    """Concentric shells of exact ties: floor(r / width) with r the distance
+    to an off-centre point, with every other shell negated, plus blocks of
+    random small integers in one octant (plateaus of several levels side by
+    side)."""
+    shape = tuple(int(s) for s in shape)
+    rng = _rng(seed)
+    idx = np.indices(shape).astype(np.float64)
+    c = [s * 0.37 for s in shape]
+    r = np.sqrt(sum((idx[i] - c[i]) ** 2 for i in range(len(shape))))
+    shell = np.floor(r / width)
+    f = np.where(shell % 2 == 0, shell, -shell)
+    blk = max(2, width)
+    coarse = rng.integers(0, 4, tuple((s + blk - 1) // blk for s in shape)).astype(np.float64)
+    for ax in range(len(shape)):
+        coarse = np.repeat(coarse, blk, axis=ax)
+    coarse = coarse[tuple(slice(0, s) for s in shape)]
+    octant = tuple(slice(0, s // 2) for s in shape)
+    f[octant] = coarse[octant]
+    return f.astype(np.float32)
+
+
+def parity_lattice(shape) -> np.ndarray:
+    """(x mod 2) + (y mod 2) + (z mod 2): the all-even vertices are the minima
+    (one vertex in eight), every value is one of four, and each minimum's basin
+    touches many others, so the in-tile table of basin pairs fills up."""
+    shape = tuple(int(s) for s in shape)
+    idx = np.indices(shape)
+    return sum(i % 2 for i in idx).astype(np.float32)
+
+
 def batch_shapes(seed: int = 4, n3: int = 32, n2: int = 16, r3=(32, 192), r2=(256, 2048)):
     """Uneven batch: n3 cubes with side log-uniform in r3, n2 squares log-uniform in r2."""
     rng = _rng(seed)

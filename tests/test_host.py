@@ -50,8 +50,9 @@ def test_face_edges_and_algorithmic_bytes():
     finally:
         mt.set_tile_shape(0, saved)
     N, P, M, Q, F = 1000, 30, 100, 50, 400
-    assert bench.algo_bytes("k_local", N, P, M) == 8 * N + 24 * M
-    assert bench.algo_bytes("k_repair_reg", N, P, M) == 16 * N
-    assert bench.algo_bytes("k_merge_q", N, P, M, Q) == 16 * Q + 16 * M
-    assert bench.algo_bytes("k_cross", N, P, M, Q, F) == 16 * F + 16 * Q
-    assert bench.algo_bytes("k_pairs_write", N, P, M) == 8 * N + 24 * P
+    assert bench.compulsory_bytes(N, P) == 12 * N + 16 * P
+    assert bench.model_bytes("k_local", N, P, M) == 8 * N + 24 * M
+    assert bench.model_bytes("k_repair_reg", N, P, M) == 16 * N
+    assert bench.model_bytes("k_merge_q", N, P, M, Q) == 16 * Q + 16 * M
+    assert bench.model_bytes("k_cross", N, P, M, Q, F) == 16 * F + 16 * Q
+    assert bench.model_bytes("k_pairs_write", N, P, M) == 8 * N + 24 * P
