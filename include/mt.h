@@ -23,8 +23,11 @@
  *    f[u] < f[w] or (f[u] == f[w] and u < w), with the IEEE comparison
  *    (-0.0 == +0.0).  The paper's definitions use strict inequalities on
  *    distinct values; the id tie-break is this library's reading for repeats.
- *  - Ids are 32-bit (Sec. 3.2 packs a pair into one 64-bit word); a field,
- *    or a whole batch, must hold fewer than 2^31 vertices.
+ *  - Ids are unsigned 32-bit inside the library (Sec. 3.2 packs a pair into
+ *    one 64-bit word, replaced by one 64-bit compare-and-swap); a field, or a
+ *    whole batch, may hold up to 2^32 - 2 vertices, each dimension below
+ *    2^31.  Ids of 2^31 and more read as negative in signed 32-bit views;
+ *    mt_build_pairs64 writes the same results with 64-bit ids.
  *  - T is uint32[N][2] = (s, v): one 8-byte-aligned 64-bit word per vertex,
  *    s in the low half.  Ids in every output are local to their field.
  *  - Pointers marked (device) are device memory on the current HIP device,
@@ -52,7 +55,7 @@ extern "C" {
 typedef enum {
     MT_OK = 0,
     MT_ERR_INVALID_ARG = -1, /* bad dims, null or misaligned pointer, bad count */
-    MT_ERR_TOO_LARGE = -2,   /* 2^31 vertices or more (32-bit ids, Sec. 3.2) */
+    MT_ERR_TOO_LARGE = -2,   /* more than 2^32 - 2 vertices, or a dimension of 2^31 or more */
     MT_ERR_NAN = -3,         /* the field holds a NaN: no order exists */
     MT_ERR_CAPACITY = -4,    /* more pairs than the output capacity */
     MT_ERR_LIVELOCK = -5,    /* a merge or chase exceeded its step cap */
@@ -161,6 +164,25 @@ int mt_build_pairs(const float *field, int64_t nx, int64_t ny, int64_t nz, int k
                    float *birth_val, float *death_val, int64_t capacity,
                    int64_t *n_pairs, int64_t *n_roots,
                    void *workspace, size_t ws_bytes, void *stream);
+
+/*
+ * mt_build_pairs64 -- mt_build_pairs with 64-bit ids in every output, for
+ * callers that index with 64-bit integers (a field may hold up to 2^32 - 2
+ * vertices, past the signed 32-bit range).  Sec. 5 names wider ids as future
+ * work; inside, the ids stay the unsigned 32-bit ones of Sec. 3.2's packed
+ * compare-and-swap word, and only the output is widened, so the triplets and
+ * pairs equal mt_build_pairs' value for value.
+ *
+ * triplets (device) uint64[N][2] = (s, v), 16-byte aligned.
+ * birth, death (device) uint64[capacity].  Every other argument, the
+ * ownership, the errors and the single synchronization are those of
+ * mt_build_pairs.
+ */
+int mt_build_pairs64(const float *field, int64_t nx, int64_t ny, int64_t nz, int kind,
+                     uint64_t *triplets, uint64_t *birth, uint64_t *death,
+                     float *birth_val, float *death_val, int64_t capacity,
+                     int64_t *n_pairs, int64_t *n_roots,
+                     void *workspace, size_t ws_bytes, void *stream);
 
 /*
  * mt_batch_build -- merge trees and pairs of many fields of uneven sizes in

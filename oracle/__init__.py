@@ -13,6 +13,11 @@ Functions (each follows the passage cited in ``oracle.c``):
 - ``pairs_scatter``: chain rule of a loss on the pair values (double).
 - ``topo_loss(f, tau)``: the simplification loss and its gradient (double).
 - ``vertex_ranks(f)``: each vertex's position in the (value, id) order (Sec. 2).
+- ``triplets_at(f, us)``: T[u] for sampled vertices u straight from the
+  definition (Sec. 2), by a bounded flood from each u, for fields too large
+  for the sweep.
+
+Ids are 64-bit throughout (uint64 outputs).
 
 Every value is handled in double precision; float32 fields are widened
 exactly before the call, which keeps the order of values unchanged.
@@ -68,6 +73,8 @@ def _load():
         lib.oracle_topo_loss.restype = ctypes.c_int
         lib.oracle_vertex_ranks.argtypes = [P, I64, P]
         lib.oracle_vertex_ranks.restype = ctypes.c_int
+        lib.oracle_triplets_at.argtypes = [P, ctypes.c_int, I64, I64, I64, P, I64, I64, P, P, P]
+        lib.oracle_triplets_at.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -91,10 +98,10 @@ def _as_f64(f) -> np.ndarray:
 
 
 def merge_tree(f) -> np.ndarray:
-    """Triplets of the merge tree of f: uint32 array [N, 2] with T[u] = (s, v)."""
+    """Triplets of the merge tree of f: uint64 array [N, 2] with T[u] = (s, v)."""
     f64 = _as_f64(f)
     nx, ny, nz = _dims(f64)
-    T = np.empty((f64.size, 2), dtype=np.uint32)
+    T = np.empty((f64.size, 2), dtype=np.uint64)
     st = _load().oracle_merge_tree(f64.ctypes.data, nx, ny, nz, T.ctypes.data)
     if st != OK:
         raise OracleError(st, "merge_tree")
@@ -104,12 +111,12 @@ def merge_tree(f) -> np.ndarray:
 def pairs(f, T: np.ndarray):
     """(birth ids, death ids, birth values, death values, n_roots), ascending birth id."""
     f64 = _as_f64(f).reshape(-1)
-    T = np.ascontiguousarray(T, dtype=np.uint32).reshape(-1, 2)
+    T = np.ascontiguousarray(T, dtype=np.uint64).reshape(-1, 2)
     N = f64.size
     lib = _load()
     cap = N // 2 + 1
-    b = np.empty(cap, np.uint32)
-    d = np.empty(cap, np.uint32)
+    b = np.empty(cap, np.uint64)
+    d = np.empty(cap, np.uint64)
     bv = np.empty(cap, np.float64)
     dv = np.empty(cap, np.float64)
     nroots = ctypes.c_int64(0)
@@ -124,8 +131,8 @@ def pairs(f, T: np.ndarray):
 
 def pairs_scatter(N: int, birth, death, gb, gd, grad=None) -> np.ndarray:
     """grad[birth[k]] += gb[k]; grad[death[k]] += gd[k] in double."""
-    birth = np.ascontiguousarray(birth, np.uint32)
-    death = np.ascontiguousarray(death, np.uint32)
+    birth = np.ascontiguousarray(birth, np.uint64)
+    death = np.ascontiguousarray(death, np.uint64)
     gb = np.ascontiguousarray(gb, np.float64)
     gd = np.ascontiguousarray(gd, np.float64)
     g = np.zeros(N, np.float64) if grad is None else np.ascontiguousarray(grad, np.float64)
@@ -150,13 +157,38 @@ def topo_loss(f, tau: float, want_grad: bool = True):
 
 
 def vertex_ranks(f) -> np.ndarray:
-    """rank[u] = number of vertices preceding u in the (value, id) order; uint32 [N]."""
+    """rank[u] = number of vertices preceding u in the (value, id) order; uint64 [N]."""
     f64 = _as_f64(f).reshape(-1)
-    r = np.empty(f64.size, np.uint32)
+    r = np.empty(f64.size, np.uint64)
     st = _load().oracle_vertex_ranks(f64.ctypes.data, f64.size, r.ctypes.data)
     if st != OK:
         raise OracleError(st, "vertex_ranks")
     return r
+
+
+def triplets_at(f, us, max_visit: int = 1 << 20):
+    """T[u] for each u in `us` by the definition (a bounded flood from u).
+
+    f: float32 or float64 array (its shape gives the grid).  Returns
+    (s, v, ok): uint64 arrays and a bool array; ok[i] is False where the flood
+    would add more than max_visit vertices (s[i], v[i] then meaningless)."""
+    a = np.asarray(f)
+    if a.dtype == np.float32:
+        is32, buf = 1, np.ascontiguousarray(a)
+    else:
+        is32, buf = 0, _as_f64(a)
+    nx, ny, nz = _dims(buf)
+    us = np.ascontiguousarray(us, dtype=np.int64).reshape(-1)
+    s = np.empty(us.size, np.uint64)
+    v = np.empty(us.size, np.uint64)
+    stat = np.empty(us.size, np.int32)
+    st = _load().oracle_triplets_at(buf.ctypes.data, is32, nx, ny, nz, us.ctypes.data, us.size, int(max_visit),
+                                    s.ctypes.data, v.ctypes.data, stat.ctypes.data)
+    if st != OK:
+        raise OracleError(st, "triplets_at")
+    if np.any(stat == ERR_NAN):
+        raise OracleError(ERR_NAN, "triplets_at")
+    return s, v, stat == OK
 
 
 def build_batch(fields):

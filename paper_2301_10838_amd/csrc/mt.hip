@@ -19,6 +19,7 @@
 #include <mutex>
 #include <string>
 #include <unordered_map>
+#include <type_traits>
 #include <vector>
 
 #include <rocprim/device/device_radix_sort.hpp>
@@ -130,6 +131,12 @@ static void read_env_locked()
 
 static int field_class(int64_t ny, int64_t nz) { return nz > 1 ? 0 : (ny > 1 ? 1 : 2); }
 
+// Ids are uint32 inside every kernel: a field, or a whole batch, holds at most
+// 2^32 - 2 vertices, so 0xffffffff and 0xfffffffe are never ids.  One
+// dimension must fit a signed 32-bit integer (the tile descriptors).
+constexpr int64_t kMaxVertices = 0xfffffffeLL;
+constexpr int64_t kMaxDim = (1LL << 31) - 1;
+
 static int make_plan(const int64_t *dims, int32_t nf, Plan &p, const int *shape_override = nullptr)
 {
     if (!dims || nf < 1) return MT_ERR_INVALID_ARG;
@@ -149,8 +156,8 @@ static int make_plan(const int64_t *dims, int32_t nf, Plan &p, const int *shape_
     for (int32_t i = 0; i < nf; ++i) {
         const int64_t nx = dims[3 * i], ny = dims[3 * i + 1], nz = dims[3 * i + 2];
         if (nx < 1 || ny < 1 || nz < 1) return MT_ERR_INVALID_ARG;
-        if (nx >= (1LL << 31) || ny >= (1LL << 31) || nz >= (1LL << 31)) return MT_ERR_TOO_LARGE;
-        if (nx * ny >= (1LL << 31) || nx * ny * nz >= (1LL << 31)) return MT_ERR_TOO_LARGE;
+        if (nx > kMaxDim || ny > kMaxDim || nz > kMaxDim) return MT_ERR_TOO_LARGE;
+        if (nx * ny > kMaxVertices || nx * ny * nz > kMaxVertices) return MT_ERR_TOO_LARGE;
         const int64_t n = nx * ny * nz;
         FieldDesc &d = p.d[i];
         d.nx = (int32_t)nx; d.ny = (int32_t)ny; d.nz = (int32_t)nz;
@@ -161,7 +168,7 @@ static int make_plan(const int64_t *dims, int32_t nf, Plan &p, const int *shape_
         chunks += (n + kChunk - 1) / kChunk;
         mcap += (n + 1) / 2;  // local minima of a tile are pairwise non-adjacent: at most
                               // half of each tile, rounded up (the tile term is added below)
-        if (off >= (1LL << 31)) return MT_ERR_TOO_LARGE;
+        if (off > kMaxVertices) return MT_ERR_TOO_LARGE;
     }
     // tile order: 3-D fields, then 2-D, then 1-D, each in field order
     int64_t tiles = 0;
@@ -192,7 +199,7 @@ static int make_plan(const int64_t *dims, int32_t nf, Plan &p, const int *shape_
         p.q_cap += (cl.ntiles + 7) / 8 * faces;
     }
     mcap += tiles;
-    if (mcap >= (1LL << 31) || p.q_cap >= (1LL << 31)) return MT_ERR_TOO_LARGE;
+    if (mcap > kMaxVertices || p.q_cap >= (1LL << 31)) return MT_ERR_TOO_LARGE;
     p.n_total = off;
     p.n_tiles = tiles;
     p.n_chunks = chunks;
@@ -364,8 +371,10 @@ static int launch_cross(const Plan &p, const ClassLaunch &cl, const Ptrs &w, con
     return MT_OK;
 }
 
-// The merge tree: triplets T (field-local ids) and, per chunk, pair counts.
-static int enqueue_build(const Plan &p, const Ptrs &w, const float *f, uint64_t *T, uint32_t flip, hipStream_t st)
+// The merge tree: triplets T (field-local ids; uint32 pairs, or uint64 pairs
+// when wide) and, per chunk, pair counts.
+static int enqueue_build(const Plan &p, const Ptrs &w, const float *f, void *T, uint32_t flip, hipStream_t st,
+                         bool wide = false)
 {
     const int nf = (int)p.d.size();
     const uint32_t n = (uint32_t)p.n_total;
@@ -401,33 +410,49 @@ static int enqueue_build(const Plan &p, const Ptrs &w, const float *f, uint64_t 
                   (uint32_t)p.q_cap, w.slot, (const uint64_t *)w.mkey, n, p.cap, flip, w.h);
     const unsigned gm = (unsigned)std::min<int64_t>(8192, std::max<int64_t>(1, (p.m_cap + kBlock - 1) / kBlock));
     MT_LAUNCH("k_repair_min", k_repair_min, dim3(gm), dim3(kBlock), st, f, w.slot, n, p.cap, flip, w.h);
-    if (p.count)
-        MT_LAUNCH("k_repair_reg", k_repair_reg<true>, dim3((unsigned)p.n_chunks), dim3(kBlock), st, f,
-                  (const uint32_t *)w.lbl, w.slot, (const uint64_t *)w.mkey, T, w.pcnt, (const FieldDesc *)w.D,
+    auto reg = [&](auto cnt, auto out) {
+        using O = decltype(out);
+        auto *const kern = &k_repair_reg<decltype(cnt)::value, O>;
+        MT_LAUNCH("k_repair_reg", kern, dim3((unsigned)p.n_chunks), dim3(kBlock), st, f, (const uint32_t *)w.lbl,
+                  w.slot, (const uint64_t *)w.mkey, (typename O::Word *)T, w.pcnt, (const FieldDesc *)w.D,
                   (const int64_t *)w.cs, nf, n, p.cap, flip, w.h);
-    else
-        MT_LAUNCH("k_repair_reg", k_repair_reg<false>, dim3((unsigned)p.n_chunks), dim3(kBlock), st, f,
-                  (const uint32_t *)w.lbl, w.slot, (const uint64_t *)w.mkey, T, w.pcnt, (const FieldDesc *)w.D,
-                  (const int64_t *)w.cs, nf, n, p.cap, flip, w.h);
+        return MT_OK;
+    };
+    using CT = std::true_type;
+    using CF = std::false_type;
+    if (wide) return p.count ? reg(CT{}, Out64{}) : reg(CF{}, Out64{});
+    return p.count ? reg(CT{}, Out32{}) : reg(CF{}, Out32{});
+}
+
+template <class O>
+static int enqueue_pairs_as(const Plan &p, const Ptrs &w, bool after_build, const float *f, const void *Tv,
+                            int64_t capacity, void *birth, void *death, float *bval, float *dval,
+                            int64_t *pair_offsets, hipStream_t st)
+{
+    const int nf = (int)p.d.size();
+    const typename O::Word *T = (const typename O::Word *)Tv;
+    if (!after_build) {
+        auto *const kc = &k_pairs_count<O>;
+        MT_LAUNCH("k_pairs_count", kc, dim3((unsigned)p.n_chunks), dim3(kBlock), st, T, (const FieldDesc *)w.D,
+                  (const int64_t *)w.cs, nf, w.pcnt, w.h);
+    }
+    MT_LAUNCH("k_pairs_scan", k_pairs_scan, dim3(1), dim3(1024), st, w.pcnt, p.n_chunks, (const FieldDesc *)w.D, nf,
+              pair_offsets, capacity, w.h);
+    auto *const kw = &k_pairs_write<O>;
+    MT_LAUNCH("k_pairs_write", kw, dim3((unsigned)p.n_chunks), dim3(kBlock), st, f, T, (const FieldDesc *)w.D,
+              (const int64_t *)w.cs, nf, (const uint32_t *)w.pcnt, capacity, (typename O::Id *)birth,
+              (typename O::Id *)death, bval, dval);
     return MT_OK;
 }
 
 // Pairs of T: counts (unless the build just counted them: its output pass
 // leaves the pair count of every chunk in the workspace), scan, ordered write.
-static int enqueue_pairs(const Plan &p, const Ptrs &w, bool after_build, const float *f, const uint64_t *T,
-                         int64_t capacity, uint32_t *birth, uint32_t *death, float *bval, float *dval,
-                         int64_t *pair_offsets, hipStream_t st)
+static int enqueue_pairs(const Plan &p, const Ptrs &w, bool after_build, const float *f, const void *T,
+                         int64_t capacity, void *birth, void *death, float *bval, float *dval,
+                         int64_t *pair_offsets, hipStream_t st, bool wide = false)
 {
-    const int nf = (int)p.d.size();
-    if (!after_build)
-        MT_LAUNCH("k_pairs_count", k_pairs_count, dim3((unsigned)p.n_chunks), dim3(kBlock), st, T,
-                  (const FieldDesc *)w.D, (const int64_t *)w.cs, nf, w.pcnt, w.h);
-    MT_LAUNCH("k_pairs_scan", k_pairs_scan, dim3(1), dim3(1024), st, w.pcnt, p.n_chunks, (const FieldDesc *)w.D, nf,
-              pair_offsets, capacity, w.h);
-    MT_LAUNCH("k_pairs_write", k_pairs_write, dim3((unsigned)p.n_chunks), dim3(kBlock), st, f, T,
-              (const FieldDesc *)w.D, (const int64_t *)w.cs, nf, (const uint32_t *)w.pcnt, capacity, birth, death,
-              bval, dval);
-    return MT_OK;
+    return wide ? enqueue_pairs_as<Out64>(p, w, after_build, f, T, capacity, birth, death, bval, dval, pair_offsets, st)
+                : enqueue_pairs_as<Out32>(p, w, after_build, f, T, capacity, birth, death, bval, dval, pair_offsets, st);
 }
 
 // Any difference between two triplet arrays latches ST_CORRUPT (autotuner check).
@@ -572,30 +597,46 @@ int mt_persistence_pairs(const float *field, const uint32_t *triplets, int64_t n
     return status_to_code(h.status);
 }
 
-int mt_build_pairs(const float *field, int64_t nx, int64_t ny, int64_t nz, int kind, uint32_t *triplets,
-                   uint32_t *birth, uint32_t *death, float *birth_val, float *death_val, int64_t capacity,
-                   int64_t *n_pairs, int64_t *n_roots, void *workspace, size_t ws_bytes, void *stream)
+static int build_pairs(const float *field, int64_t nx, int64_t ny, int64_t nz, int kind, void *triplets,
+                       void *birth, void *death, float *birth_val, float *death_val, int64_t capacity,
+                       int64_t *n_pairs, int64_t *n_roots, void *workspace, size_t ws_bytes, void *stream, bool wide)
 {
     if (kind != MT_TREE_MERGE && kind != MT_TREE_SPLIT) return MT_ERR_INVALID_ARG;
     const int64_t dims[3] = {nx, ny, nz};
     Plan p;
     int rc = make_plan(dims, 1, p);
     if (rc != MT_OK) return rc;
-    if (!field || !triplets || ((uintptr_t)triplets & 7u) || !n_pairs || capacity < 0) return MT_ERR_INVALID_ARG;
+    const uintptr_t talign = wide ? 15u : 7u;
+    if (!field || !triplets || ((uintptr_t)triplets & talign) || !n_pairs || capacity < 0) return MT_ERR_INVALID_ARG;
     if (capacity > 0 && (!birth || !death || !birth_val || !death_val)) return MT_ERR_INVALID_ARG;
     if ((rc = check_ws(p, workspace, ws_bytes)) != MT_OK) return rc;
     hipStream_t st = (hipStream_t)stream;
     const Ptrs w = ws_ptrs(p, workspace);
     if ((rc = enqueue_setup(p, w, ~0u, true, st)) != MT_OK) return rc;
-    if ((rc = enqueue_build(p, w, field, (uint64_t *)triplets, kind_flip(kind), st)) != MT_OK) return rc;
-    rc = enqueue_pairs(p, w, true, field, (const uint64_t *)triplets, capacity, birth, death, birth_val, death_val,
-                       nullptr, st);
+    if ((rc = enqueue_build(p, w, field, triplets, kind_flip(kind), st, wide)) != MT_OK) return rc;
+    rc = enqueue_pairs(p, w, true, field, triplets, capacity, birth, death, birth_val, death_val, nullptr, st, wide);
     if (rc != MT_OK) return rc;
     Header h;
     if ((rc = read_header(workspace, st, h)) != MT_OK) return rc;
     *n_pairs = h.total_pairs;
     if (n_roots) *n_roots = h.roots;
     return status_to_code(h.status);
+}
+
+int mt_build_pairs(const float *field, int64_t nx, int64_t ny, int64_t nz, int kind, uint32_t *triplets,
+                   uint32_t *birth, uint32_t *death, float *birth_val, float *death_val, int64_t capacity,
+                   int64_t *n_pairs, int64_t *n_roots, void *workspace, size_t ws_bytes, void *stream)
+{
+    return build_pairs(field, nx, ny, nz, kind, triplets, birth, death, birth_val, death_val, capacity, n_pairs,
+                       n_roots, workspace, ws_bytes, stream, false);
+}
+
+int mt_build_pairs64(const float *field, int64_t nx, int64_t ny, int64_t nz, int kind, uint64_t *triplets,
+                     uint64_t *birth, uint64_t *death, float *birth_val, float *death_val, int64_t capacity,
+                     int64_t *n_pairs, int64_t *n_roots, void *workspace, size_t ws_bytes, void *stream)
+{
+    return build_pairs(field, nx, ny, nz, kind, triplets, birth, death, birth_val, death_val, capacity, n_pairs,
+                       n_roots, workspace, ws_bytes, stream, true);
 }
 
 int mt_batch_build(const float *fields, const int64_t *dims, int32_t n_fields, uint32_t *triplets, uint32_t *birth,
@@ -684,8 +725,7 @@ struct RankLayout {
 int rank_layout(int64_t nx, int64_t ny, int64_t nz, RankLayout &L)
 {
     if (nx < 1 || ny < 1 || nz < 1) return MT_ERR_INVALID_ARG;
-    if (nx >= (1LL << 31) || ny >= (1LL << 31) || nz >= (1LL << 31) || nx * ny >= (1LL << 31) ||
-        nx * ny * nz >= (1LL << 31))
+    if (nx > kMaxDim || ny > kMaxDim || nz > kMaxDim || nx * ny > kMaxVertices || nx * ny * nz > kMaxVertices)
         return MT_ERR_TOO_LARGE;
     const size_t n = (size_t)(nx * ny * nz);
     size_t tmp = 0;  // a size query: nothing is launched
@@ -948,11 +988,11 @@ int mt_pairs_backward(const int64_t *dims, int32_t n_fields, const int64_t *pair
     for (int32_t i = 0; i < n_fields; ++i) {
         const int64_t nx = dims[3 * i], ny = dims[3 * i + 1], nz = dims[3 * i + 2];
         if (nx < 1 || ny < 1 || nz < 1) return MT_ERR_INVALID_ARG;
-        if (nx >= (1LL << 31) || ny >= (1LL << 31) || nz >= (1LL << 31)) return MT_ERR_TOO_LARGE;
-        if (nx * ny * nz >= (1LL << 31)) return MT_ERR_TOO_LARGE;
+        if (nx > kMaxDim || ny > kMaxDim || nz > kMaxDim) return MT_ERR_TOO_LARGE;
+        if (nx * ny > kMaxVertices || nx * ny * nz > kMaxVertices) return MT_ERR_TOO_LARGE;
         voff[i] = off;
         off += nx * ny * nz;
-        if (off >= (1LL << 31)) return MT_ERR_TOO_LARGE;
+        if (off > kMaxVertices) return MT_ERR_TOO_LARGE;
     }
     voff[n_fields] = off;
     hipStream_t st = (hipStream_t)stream;

@@ -209,6 +209,35 @@ __device__ __forceinline__ uint32_t lo32(uint64_t t) { return (uint32_t)t; }
 __device__ __forceinline__ uint32_t hi32(uint64_t t) { return (uint32_t)(t >> 32); }
 __device__ __forceinline__ uint64_t pack(uint32_t s, uint32_t v) { return (uint64_t)s | ((uint64_t)v << 32); }
 
+// Output id width.  Internally every id is a uint32 (a batch holds fewer than
+// 2^32 - 1 vertices); the output either keeps that width (T[u] = one 64-bit
+// word (s, v), the packing of Sec. 3.2, pair ids uint32) or widens it for
+// callers that index with 64-bit integers (T[u] = two uint64 in one 16-byte
+// word, pair ids uint64).
+struct Out32 {
+    using Id = uint32_t;
+    using Word = uint64_t;
+    __device__ static void store(Word *T, uint32_t u, uint32_t s, uint32_t v) { T[u] = pack(s, v); }
+    __device__ static void load(const Word *T, uint32_t u, uint32_t &s, uint32_t &v)
+    {
+        const uint64_t t = T[u];
+        s = lo32(t);
+        v = hi32(t);
+    }
+};
+struct Out64 {
+    using Id = uint64_t;
+    using Word = ulonglong2;
+    __device__ static void store(Word *T, uint32_t u, uint32_t s, uint32_t v) { T[u] = make_ulonglong2(s, v); }
+    __device__ static void load(const Word *T, uint32_t u, uint32_t &s, uint32_t &v)
+    {
+        const ulonglong2 t = T[u];
+        // ids written by this library fit 32 bits; anything else fails the range checks
+        s = t.x >> 32 ? 0xffffffffu : (uint32_t)t.x;
+        v = t.y >> 32 ? 0xffffffffu : (uint32_t)t.y;
+    }
+};
+
 // Untorn 64-bit read/write of a slot word.  The merge phase reads through the
 // cache: a stale triplet is a fact that held earlier and still holds, and
 // the compare-and-swap, which always sees the current word, hands back the
@@ -467,7 +496,7 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
     const TileCtx c = tile_ctx<S>(D, tfield, tstart, nfc, tile0 + tl);
     const uint32_t off = (uint32_t)c.d.offset;
     auto valid = [&](int lx, int ly, int lz) { return lx < c.ex && ly < c.ey && lz < c.ez; };
-    // Ids in 32 bits: every id of the batch is below 2^31.
+    // Ids in 32 bits: every id of the batch is below 2^32 - 2.
     const uint32_t nx = (uint32_t)c.d.nx, sxy = (uint32_t)c.sxy;
     const uint32_t base = off + (uint32_t)c.x0 + nx * (uint32_t)c.y0 + sxy * (uint32_t)c.z0;
     auto lid = [&](int lx, int ly, int lz) { return (uint32_t)lx + nx * (uint32_t)ly + sxy * (uint32_t)lz; };
@@ -1220,10 +1249,10 @@ __global__ __launch_bounds__(kBlock) void k_repair_min(const float *__restrict__
 // vertices at once, so the dependent loads of their chases (label -> slot ->
 // slot ... -> minimum key) overlap.
 constexpr int RV = 4;
-template <bool CNT>
+template <bool CNT, class O>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_repair_reg(const float *__restrict__ f, const uint32_t *__restrict__ lbl,
                                                        const Slot *__restrict__ S, const uint64_t *__restrict__ mkey,
-                                                       uint64_t *__restrict__ T, uint32_t *__restrict__ pcnt,
+                                                       typename O::Word *__restrict__ T, uint32_t *__restrict__ pcnt,
                                                        const FieldDesc *__restrict__ D, const int64_t *__restrict__ cs,
                                                        int nf, uint32_t n, uint32_t cap, uint32_t flip,
                                                        Header *__restrict__ h)
@@ -1326,7 +1355,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
         for (int i = 0; i < RV; ++i) {
             if (!((live >> i) & 1u)) continue;
             if (gr[i] >= n) { err |= ST_CORRUPT; continue; }
-            T[u[i]] = pack(s[i] - off, gr[i] - off);
+            O::store(T, u[i], s[i] - off, gr[i] - off);
         }
     }
     for (int o = 32; o > 0; o >>= 1) {
@@ -1350,11 +1379,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
 
 // Ids read from T are checked to lie in the field; a bad one is no pair and
 // latches ST_CORRUPT.
-__device__ __forceinline__ bool classify(const uint64_t *__restrict__ T, uint32_t off, uint32_t nloc, int64_t j,
-                                         uint32_t &s_out, bool &root, uint32_t &err)
+template <class O>
+__device__ __forceinline__ bool classify(const typename O::Word *__restrict__ T, uint32_t off, uint32_t nloc,
+                                         int64_t j, uint32_t &s_out, bool &root, uint32_t &err)
 {
-    const uint64_t t = T[off + (uint32_t)j];
-    const uint32_t s = lo32(t), v = hi32(t);
+    uint32_t s, v;
+    O::load(T, off + (uint32_t)j, s, v);
     root = false;
     if (s >= nloc || v >= nloc) { err |= ST_CORRUPT; return false; }
     if (s == (uint32_t)j) { root = (v == (uint32_t)j); return false; }
@@ -1362,7 +1392,8 @@ __device__ __forceinline__ bool classify(const uint64_t *__restrict__ T, uint32_
     return true;
 }
 
-__global__ __launch_bounds__(kBlock) void k_pairs_count(const uint64_t *__restrict__ T,
+template <class O>
+__global__ __launch_bounds__(kBlock) void k_pairs_count(const typename O::Word *__restrict__ T,
                                                         const FieldDesc *__restrict__ D, const int64_t *__restrict__ cs,
                                                         int nf, uint32_t *__restrict__ cnt, Header *__restrict__ h)
 {
@@ -1375,7 +1406,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs_count(const uint64_t *__restri
     for (int64_t j = lo + threadIdx.x; j < hi; j += kBlock) {
         uint32_t s;
         bool root;
-        np += classify(T, (uint32_t)d.offset, (uint32_t)d.n, j, s, root, err) ? 1u : 0u;
+        np += classify<O>(T, (uint32_t)d.offset, (uint32_t)d.n, j, s, root, err) ? 1u : 0u;
         nr += root ? 1u : 0u;
     }
     if (err) atomicOr(&h->status, err);
@@ -1488,10 +1519,13 @@ __device__ __forceinline__ uint32_t select_bit(uint64_t m, uint32_t k)
 // shares the wave totals.  Then lane k of a pass takes the wave's k-th pair
 // (its word by the word counts' prefix, its bit by halving), so the value
 // gathers and the stores run on dense lanes, 64 consecutive pairs a pass.
-__global__ __launch_bounds__(kBlock) void k_pairs_write(const float *__restrict__ f, const uint64_t *__restrict__ T,
+template <class O>
+__global__ __launch_bounds__(kBlock) void k_pairs_write(const float *__restrict__ f,
+                                                        const typename O::Word *__restrict__ T,
                                                         const FieldDesc *__restrict__ D, const int64_t *__restrict__ cs,
                                                         int nf, const uint32_t *__restrict__ base, int64_t capacity,
-                                                        uint32_t *__restrict__ birth, uint32_t *__restrict__ death,
+                                                        typename O::Id *__restrict__ birth,
+                                                        typename O::Id *__restrict__ death,
                                                         float *__restrict__ bval, float *__restrict__ dval)
 {
     constexpr int WSPAN = kChunk / (kBlock / 64);  // vertices per wave
@@ -1515,7 +1549,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs_write(const float *__restrict_
         sl[r] = 0;
         if (j < hi) {
             bool root;
-            pf[r] = classify(T, off, nloc, j, sl[r], root, err);
+            pf[r] = classify<O>(T, off, nloc, j, sl[r], root, err);
         }
     }
     uint64_t wd = 0;  // lane r < NWD: the ballot word of vertices w0 + 64 r + [0, 64)

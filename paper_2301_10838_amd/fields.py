@@ -113,6 +113,43 @@ def lognormal_grf(shape, seed: int, slope: float = -3.0) -> np.ndarray:
     return np.exp(g).astype(np.float32)
 
 
+def lognormal_grf_device(shape, seed: int, device, slope: float = -3.0):
+    """The lognormal_grf recipe computed on a device with torch (float32 FFTs),
+    for fields too large for a host FFT (e.g. 1300^3, 2.2 G vertices).
+
+    Seeded with torch's generator on that device, so its values differ from
+    lognormal_grf's for the same seed; returns a float32 torch tensor."""
+    import torch
+
+    shape = tuple(int(s) for s in shape)
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    x = torch.randn(shape, generator=g, device=device, dtype=torch.float32)
+    X = torch.fft.rfftn(x)
+    del x
+    k2 = None
+    for ax, n in enumerate(shape):
+        if ax == len(shape) - 1:
+            k = torch.fft.rfftfreq(n, device=device) * n
+        else:
+            k = torch.fft.fftfreq(n, device=device) * n
+        sh = [1] * len(shape)
+        sh[ax] = k.numel()
+        t = (k * k).reshape(sh)
+        k2 = t if k2 is None else k2 + t
+    amp = torch.where(k2 > 0, k2.clamp_min(1e-30) ** (slope / 4.0), torch.zeros_like(k2))
+    del k2
+    X *= amp
+    del amp
+    y = torch.fft.irfftn(X, s=shape)
+    del X
+    y -= y.mean(dtype=torch.float64).float()
+    sd = y.std().float()
+    if float(sd) > 0:
+        y /= sd
+    return torch.exp_(y)
+
+
 # Adversarial structure ------------------------------------------------------
 #
 # Fields built to stress the parts of the build that the smooth workloads

@@ -34,7 +34,7 @@ EXPORTS = [
     "mt_set_tile_shape", "mt_get_tile_shape", "mt_autotune_workspace_bytes", "mt_autotune", "mt_build_tree",
     "mt_batch_build_tree", "mt_build_pairs", "mt_vertex_ranks", "mt_rank_workspace_bytes",
     "mt_set_max_steps", "mt_get_max_steps", "mt_set_table_probes", "mt_get_table_probes", "mt_workspace_reset",
-    "mt_set_counting", "mt_get_counting", "mt_read_counters",
+    "mt_set_counting", "mt_get_counting", "mt_read_counters", "mt_build_pairs64",
 ]
 
 COUNTER_NAMES = [
@@ -88,6 +88,8 @@ def load_library():
     lib.mt_persistence_pairs.restype = ctypes.c_int
     lib.mt_build_pairs.argtypes = [P, I64, I64, I64, ctypes.c_int, P, P, P, P, P, I64, P, P, P, SZ, P]
     lib.mt_build_pairs.restype = ctypes.c_int
+    lib.mt_build_pairs64.argtypes = [P, I64, I64, I64, ctypes.c_int, P, P, P, P, P, I64, P, P, P, SZ, P]
+    lib.mt_build_pairs64.restype = ctypes.c_int
     lib.mt_vertex_ranks.argtypes = [P, I64, I64, I64, ctypes.c_int, P, P, SZ, P]
     lib.mt_vertex_ranks.restype = ctypes.c_int
     lib.mt_rank_workspace_bytes.argtypes = [I64, I64, I64]
@@ -270,6 +272,35 @@ def mt_build_pairs(field: torch.Tensor, kind="merge", capacity: int | None = Non
                             death.data_ptr(), bval.data_ptr(), dval.data_ptr(), capacity, ctypes.byref(n_pairs),
                             ctypes.byref(n_roots), workspace.data_ptr(), workspace.numel(), _stream_ptr(dev))
     _check(rc, "mt_build_pairs")
+    P = n_pairs.value
+    return triplets, birth[:P], death[:P], bval[:P], dval[:P], n_roots.value
+
+
+def mt_build_pairs64(field: torch.Tensor, kind="merge", capacity: int | None = None,
+                     triplets: torch.Tensor | None = None, workspace: torch.Tensor | None = None):
+    """mt_build_pairs with 64-bit ids: (triplets int64 [N, 2], birth, death
+    (int64), birth_val, death_val, n_roots)."""
+    lib = load_library()
+    f = _field(field)
+    nx, ny, nz = grid_dims(f.shape)
+    N = nx * ny * nz
+    if capacity is None:
+        capacity = N // 2 + 1
+    dev = f.device
+    if triplets is None:
+        triplets = torch.empty((N, 2), dtype=torch.int64, device=dev)
+    birth = torch.empty(max(capacity, 1), dtype=torch.int64, device=dev)
+    death = torch.empty_like(birth)
+    bval = torch.empty(max(capacity, 1), dtype=torch.float32, device=dev)
+    dval = torch.empty_like(bval)
+    if workspace is None:
+        workspace = alloc_workspace(lib.mt_workspace_bytes(nx, ny, nz), dev)
+    n_pairs = ctypes.c_int64(0)
+    n_roots = ctypes.c_int64(0)
+    rc = lib.mt_build_pairs64(f.data_ptr(), nx, ny, nz, _kind(kind), triplets.data_ptr(), birth.data_ptr(),
+                              death.data_ptr(), bval.data_ptr(), dval.data_ptr(), capacity, ctypes.byref(n_pairs),
+                              ctypes.byref(n_roots), workspace.data_ptr(), workspace.numel(), _stream_ptr(dev))
+    _check(rc, "mt_build_pairs64")
     P = n_pairs.value
     return triplets, birth[:P], death[:P], bval[:P], dval[:P], n_roots.value
 

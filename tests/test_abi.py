@@ -13,7 +13,7 @@ HEADER = os.path.join(ROOT, "include", "mt.h")
 def _declared():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(mt_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(mt_[a-z0-9_]+)\s*\(", src)))
 
 
 @pytest.fixture(scope="module")
@@ -43,8 +43,10 @@ def test_status_strings(lib):
 
 def test_workspace_sizes(lib):
     assert lib.mt_workspace_bytes(0, 1, 1) == 0
-    assert lib.mt_workspace_bytes(1 << 31, 1, 1) == 0
-    assert lib.mt_workspace_bytes(2048, 1024, 1024) == 0  # 2^31 vertices
+    assert lib.mt_workspace_bytes(1 << 31, 1, 1) == 0  # one dimension of 2^31
+    assert lib.mt_workspace_bytes(4096, 1024, 1024) == 0  # 2^32 vertices
+    assert lib.mt_workspace_bytes(65536, 65535, 1) > 0  # 2^32 - 65536 vertices: ids up to 2^32 - 2
+    assert lib.mt_workspace_bytes(2048, 1024, 1024) > 0  # 2^31 vertices
     w = lib.mt_workspace_bytes(64, 64, 64)
     assert w >= 4 * 64 ** 3 and w % 256 == 0
     dims = (ctypes.c_int64 * 6)(64, 64, 64, 100, 90, 1)
@@ -60,7 +62,13 @@ def test_host_argument_checks(lib):
     assert lib.mt_build(fake, 0, 8, 8, fake, fake, ws, None) == -1
     assert lib.mt_build(fake, -3, 8, 8, fake, fake, ws, None) == -1
     # too many vertices for 32-bit ids
-    assert lib.mt_build(fake, 1 << 16, 1 << 15, 1, fake, fake, ws, None) == -2
+    assert lib.mt_build(fake, 1 << 16, 1 << 16, 1, fake, fake, ws, None) == -2
+    # the 64-bit output variant wants 16-byte aligned triplets
+    n = ctypes.c_int64(0)
+    assert lib.mt_build_pairs64(fake, 8, 8, 8, 0, ctypes.c_void_p(0x10008), fake, fake, fake, fake, 10,
+                                ctypes.byref(n), None, fake, ws, None) == -1
+    assert lib.mt_build_pairs64(fake, 1 << 16, 1 << 16, 1, 0, fake, fake, fake, fake, fake, 10, ctypes.byref(n),
+                                None, fake, ws, None) == -2
     # null / misaligned triplets
     assert lib.mt_build(fake, 8, 8, 8, None, fake, ws, None) == -1
     assert lib.mt_build(fake, 8, 8, 8, ctypes.c_void_p(0x10004), fake, ws, None) == -1
@@ -87,10 +95,10 @@ def test_host_argument_checks(lib):
     # vertex ranks: kind, dims, null ranks, workspace
     rws = lib.mt_rank_workspace_bytes(8, 8, 8)
     assert rws > 16 * 512 and lib.mt_rank_workspace_bytes(0, 8, 8) == 0
-    assert lib.mt_rank_workspace_bytes(1 << 16, 1 << 15, 1) == 0
+    assert lib.mt_rank_workspace_bytes(1 << 16, 1 << 16, 1) == 0
     assert lib.mt_vertex_ranks(fake, 8, 8, 8, 2, fake, fake, rws, None) == -1
     assert lib.mt_vertex_ranks(fake, 8, 0, 8, 0, fake, fake, rws, None) == -1
-    assert lib.mt_vertex_ranks(fake, 1 << 16, 1 << 15, 1, 0, fake, fake, rws, None) == -2
+    assert lib.mt_vertex_ranks(fake, 1 << 16, 1 << 16, 1, 0, fake, fake, rws, None) == -2
     assert lib.mt_vertex_ranks(fake, 8, 8, 8, 0, None, fake, rws, None) == -1
     assert lib.mt_vertex_ranks(fake, 8, 8, 8, 1, fake, fake, rws - 1, None) == -6
     assert lib.mt_vertex_ranks(fake, 8, 8, 8, 1, fake, ctypes.c_void_p(0x10010), rws, None) == -6
@@ -98,7 +106,7 @@ def test_host_argument_checks(lib):
     dims = (ctypes.c_int64 * 3)(8, 0, 8)
     assert lib.mt_batch_build(fake, dims, 1, fake, fake, fake, fake, fake, 10, fake, fake, 1 << 20, None) == -1
     assert lib.mt_batch_build(fake, dims, 0, fake, fake, fake, fake, fake, 10, fake, fake, 1 << 20, None) == -1
-    big = (ctypes.c_int64 * 6)(1 << 15, 1 << 15, 1, 1 << 15, 1 << 15, 1)
+    big = (ctypes.c_int64 * 6)(1 << 16, 1 << 15, 1, 1 << 16, 1 << 15, 1)  # 2^32 vertices in all
     assert lib.mt_batch_build(fake, big, 2, fake, fake, fake, fake, fake, 10, fake, fake, 1 << 20, None) == -2
     # tree kind: only merge (0) and split (1)
     good = (ctypes.c_int64 * 3)(8, 8, 8)

@@ -350,3 +350,96 @@ def test_vertex_ranks_permutation_and_reversal():
 def test_vertex_ranks_nan_rejected():
     with pytest.raises(oracle.OracleError):
         oracle.vertex_ranks(np.array([1.0, np.nan], np.float32))
+
+
+# --- 64-bit ids --------------------------------------------------------------
+
+def test_ids_are_64_bit():
+    """Every id the oracle returns is uint64, and the sweep's values do not
+    depend on the width (the hand example E4 as uint64)."""
+    f = np.array([5, 1, 6, 2, 9, 3, 7, 4, 8], np.float32).reshape(3, 3)
+    T = oracle.merge_tree(f)
+    assert T.dtype == np.uint64
+    b, d, _, _, _ = oracle.pairs(f, T)
+    assert b.dtype == np.uint64 and d.dtype == np.uint64
+    assert T.tolist() == [[0, 1], [1, 1], [2, 1], [0, 1], [4, 1], [2, 1], [6, 1], [6, 1], [8, 1]]
+    assert oracle.vertex_ranks(f).dtype == np.uint64
+
+
+# --- one triplet from its definition (the flood), against the sweep -----------
+
+@pytest.mark.parametrize("maker", [
+    lambda: fields.uniform((9, 10, 11), 1),
+    lambda: fields.lognormal_grf((20, 21, 22), 2),
+    lambda: np.random.default_rng(3).integers(0, 3, (7, 8, 9)).astype(np.float32),
+    lambda: fields.plateau_jump((10, 11, 12), 4),
+    lambda: fields.lognormal_grf((60, 70), 5),
+    lambda: fields.uniform((300,), 6),
+    lambda: np.array([[np.inf, 0.0, -0.0, 1.0], [-np.inf, -0.0, 0.0, np.inf]], np.float32),
+    lambda: fields.serpentine((6, 7, 9), 7),
+])
+def test_triplets_at_equals_sweep_everywhere(maker):
+    """The flood computes every triplet of small fields exactly as the sweep
+    does: two independent constructions of the same definition (a sorted
+    union-find sweep over the whole field, and a priority flood from one
+    vertex), in float32 and float64 input."""
+    f = maker()
+    T = oracle.merge_tree(f)
+    us = np.arange(f.size)
+    for arr in (f, f.astype(np.float64)):
+        s, v, ok = oracle.triplets_at(arr, us, max_visit=1 << 16)
+        assert ok.all()
+        assert np.array_equal(s, T[:, 0]) and np.array_equal(v, T[:, 1])
+
+
+def test_triplets_at_reports_budget():
+    """A flood that would add more than max_visit vertices is flagged, not
+    answered; the ones that fit agree with the sweep."""
+    f = fields.lognormal_grf((40, 40, 40), 8)
+    T = oracle.merge_tree(f)
+    us = np.random.default_rng(9).integers(0, f.size, 500)
+    s, v, ok = oracle.triplets_at(f, us, max_visit=64)
+    assert 0 < ok.sum() < ok.size
+    assert np.array_equal(s[ok], T[us[ok], 0]) and np.array_equal(v[ok], T[us[ok], 1])
+    with pytest.raises(oracle.OracleError):
+        oracle.triplets_at(np.array([1.0, np.nan, 0.5], np.float32), [0, 1, 2])
+
+
+# --- closed forms of the adversarial generators --------------------------------
+
+def test_parity_lattice_minima():
+    """(x mod 2) + (y mod 2) + (z mod 2): the all-even vertices are exactly the
+    minima, so #pairs = ceil(nx/2) ceil(ny/2) ceil(nz/2) - 1."""
+    for shape in [(6, 7, 9), (5, 5, 5), (2, 9, 4)]:
+        f = fields.parity_lattice(shape)
+        T = oracle.merge_tree(f)
+        b, _, _, _, roots = oracle.pairs(f, T)
+        want = int(np.prod([(n + 1) // 2 for n in shape])) - 1
+        assert b.size == want and roots == 1
+        z, y, x = np.unravel_index(b.astype(np.int64), shape)
+        assert np.all((x % 2 == 0) & (y % 2 == 0) & (z % 2 == 0))
+
+
+def test_tilted_checkerboard_minima():
+    """Every even-parity vertex is a minimum (all its neighbours sit one unit
+    higher), so #pairs = ceil(N/2) - 1, and the global minimum is vertex 0."""
+    for shape in [(7, 8, 9), (11, 13)]:
+        f = fields.tilted_checkerboard(shape, 3)
+        T = oracle.merge_tree(f)
+        b, _, _, _, roots = oracle.pairs(f, T)
+        assert b.size == (f.size + 1) // 2 - 1 and roots == 1
+        assert T[0].tolist() == [0, 0]
+
+
+def test_serpentine_2d_single_branch():
+    """In 2-D every vertex off the path touches it, so the path's start is the
+    only minimum: no pairs, and every vertex's target is the start (its
+    reverse for the descending path)."""
+    f = fields.serpentine((9, 12), 5)
+    T = oracle.merge_tree(f)
+    assert oracle.pairs(f, T)[0].size == 0
+    assert np.all(T[:, 1] == 0)
+    g = fields.serpentine((9, 12), 5, descending=True)
+    Tg = oracle.merge_tree(g)
+    end = int(np.argmin(g))
+    assert oracle.pairs(g, Tg)[0].size == 0 and np.all(Tg[:, 1] == end)
