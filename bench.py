@@ -212,6 +212,45 @@ def cpu_baseline(f: np.ndarray, T_gpu: np.ndarray, birth_gpu: np.ndarray, death_
     }
 
 
+def atomic_rates(s, mt, kstats, dev):
+    """Compare-and-swap rates of the merge kernels against the measured
+    ceilings: one counting build of the timed field (outside the timed
+    region) gives the swaps each kernel issues per launch; divided by the
+    kernel's average time from the timed kernels' pass."""
+    from paper_2301_10838_amd import micro
+
+    ceil = micro.ceilings(dev)
+    mt.set_counting(True)
+    try:
+        s.build_stats()
+        c = mt.read_counters(s.ws)
+    finally:
+        mt.set_counting(False)
+    s.step()  # the timed kernels again (restores nothing: the output is the same)
+
+    def avg_s(k):
+        return kstats[k][0] / kstats[k][1] / 1e3 if k in kstats else None
+
+    out = {"counts": c}
+    t = avg_s("k_merge_q")
+    if t:
+        rate = c["gm_cas"] / t / 1e9
+        peak = ceil["cas_Gops"]["mall_128MiB"]
+        out["k_merge_q"] = {"cas_per_launch": c["gm_cas"], "cas_fail_frac": c["gm_cas_fail"] / max(1, c["gm_cas"]),
+                            "Gcas_per_s": rate, "peak_Gcas_per_s": peak, "frac": rate / peak,
+                            "steps_per_fact": c["gm_steps"] / max(1, c["gm_facts"]),
+                            "peak_note": "uncontended random 64-bit CAS over 128 MiB (cache-resident, like the slots)"}
+    t = avg_s("k_local")
+    if t:
+        ops = c["lds_cas"] + c["table_probes"]  # LDS compare-and-swaps and atomic-min probes
+        rate = ops / t / 1e9
+        peak = ceil["lds_cas_Gops"]
+        out["k_local"] = {"lds_atomics_per_launch": ops, "lds_cas_fail_frac": c["lds_cas_fail"] / max(1, c["lds_cas"]),
+                          "Gops_per_s": rate, "peak_Gops_per_s": peak, "frac": rate / peak,
+                          "steps_per_merge": c["lds_steps"] / max(1, c["lds_merges"])}
+    return ceil, out
+
+
 def bench_batch(dev, mt, lib, reps: int = 5):
     """The uneven 48-field batch: one graph launch against per-field calls,
     both the synchronous fused call (mt_build_pairs, which waits for its pair
@@ -678,6 +717,10 @@ def main():
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = {"read": src.numel() * 4, "write": dst.numel() * 4}
         del src, dst
+    if not args.no_secondary:
+        out["ceilings"], out["atomics"] = atomic_rates(s, mt, kstats, dev)
+        if dom in out["atomics"]:
+            roofline["atomic"] = out["atomics"][dom]
     T_host = s.T.cpu().numpy().view(np.uint32).reshape(-1, 2)
     b_host = s.b[:P].cpu().numpy().view(np.uint32)
     d_host = s.d[:P].cpu().numpy().view(np.uint32)

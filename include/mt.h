@@ -361,7 +361,7 @@ int mt_get_table_probes(void);
  *
  * mt_read_counters synchronizes `stream` and copies the counters of the last
  * build on `workspace` into counts (host, uint64[n]); it returns how many it
- * wrote (at most 16; the rest of counts is zeroed) or an error.  In order:
+ * wrote (at most 18; the rest of counts is zeroed) or an error.  In order:
  *   0 cross-tile merges started (one per queued fact)
  *   1 iterations of the cross-tile merge loop (Alg. 3)
  *   2 of those, descent steps
@@ -378,6 +378,9 @@ int mt_get_table_probes(void);
  *  13 table probes (one LDS atomic minimum each)
  *  14 in-tile edges merged without the table
  *  15 chase steps of the output pass (Alg. 4 for every regular vertex)
+ *  16 path compressions in long cross-tile descents (a link re-pointed past
+ *     the next one when that one's saddle is not higher, one Repair step)
+ *  17 chase steps of the minimum repair (Alg. 5 for every local minimum)
  * Only a counting build writes them; after a timed build they read 0.
  */
 int mt_set_counting(int on);

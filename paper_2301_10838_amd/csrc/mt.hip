@@ -409,7 +409,10 @@ static int enqueue_build(const Plan &p, const Ptrs &w, const float *f, void *T, 
         MT_LAUNCH("k_merge_q", k_merge_q<false>, dim3(gq), dim3(kBlock), st, f, (const Fact *)w.qbin,
                   (uint32_t)p.q_cap, w.slot, (const uint64_t *)w.mkey, n, p.cap, flip, w.h);
     const unsigned gm = (unsigned)std::min<int64_t>(8192, std::max<int64_t>(1, (p.m_cap + kBlock - 1) / kBlock));
-    MT_LAUNCH("k_repair_min", k_repair_min, dim3(gm), dim3(kBlock), st, f, w.slot, n, p.cap, flip, w.h);
+    if (p.count)
+        MT_LAUNCH("k_repair_min", k_repair_min<true>, dim3(gm), dim3(kBlock), st, f, w.slot, n, p.cap, flip, w.h);
+    else
+        MT_LAUNCH("k_repair_min", k_repair_min<false>, dim3(gm), dim3(kBlock), st, f, w.slot, n, p.cap, flip, w.h);
     auto reg = [&](auto cnt, auto out) {
         using O = decltype(out);
         auto *const kern = &k_repair_reg<decltype(cnt)::value, O>;

@@ -120,6 +120,8 @@ enum CtrId {
     C_TAB_PROBES,     // atomic-min probes of those inserts
     C_TAB_DIRECT,     // edges merged without the table (no room, or no table)
     C_REG_CHASES,     // chase steps of the output pass
+    C_GM_COMPRESS,    // path compressions in cross-tile descents
+    C_MIN_CHASES,     // chase steps of the minimum repair
     kCtr
 };
 __host__ __device__ constexpr bool ctr_is_max(int i) { return i == C_GM_MAX_STEPS || i == C_LDS_MAX_STEPS; }
@@ -831,6 +833,34 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
 // ---------------------------------------------------------------------------
 // 2. Merge (Alg. 3) across tiles, on the minimum slots
 
+// Path compression in long descents.  When a descent has followed x -> y (at
+// saddle sx) and is about to follow y -> z at a saddle sy not above sx, x is
+// re-pointed at z at its own saddle, (sx, y) -> (sx, z), by compare-and-swap:
+// x and z are connected at the level of sx through y and z lies below y, so
+// this is one step of Repair's chase (Alg. 4) written back early, and a swap
+// that finds x changed does nothing.  Merged in ascending saddle order only
+// approximately (the facts are binned by their top key bits), a monotone path
+// through many tiles otherwise builds chains that every later merge walks to
+// the end: quadratic in the path length.  Merges that stay short (the common
+// case) never pay the extra swap.
+constexpr uint32_t kCompressAfter = 8;
+
+struct Link {  // the link a descent followed last: x -> hi32(w) at the saddle with key k
+    uint32_t x = 0xffffffffu;
+    uint64_t w = 0, k = 0;
+};
+
+template <bool CNT>
+__device__ __forceinline__ void compress(Slot *__restrict__ S, const Link &l, uint32_t y, uint64_t ky, uint32_t z,
+                                         uint32_t desc, Tally<CNT> &tc)
+{
+    if (desc <= kCompressAfter || l.x == 0xffffffffu || hi32(l.w) != y || ky > l.k) return;
+    uint64_t e = l.w;
+    if (__hip_atomic_compare_exchange_strong(&S[l.x].w, &e, pack(lo32(l.w), z), __ATOMIC_RELAXED,
+                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+        tc.add(C_GM_COMPRESS);
+}
+
 template <bool CNT>
 __device__ void gmerge(Slot *__restrict__ S, const uint64_t *__restrict__ mkey, const float *__restrict__ f,
                        uint32_t flip, uint32_t M, uint32_t n, uint32_t u, uint32_t s, uint64_t ks, uint32_t v,
@@ -839,22 +869,34 @@ __device__ void gmerge(Slot *__restrict__ S, const uint64_t *__restrict__ mkey, 
     tc.add(C_GM_FACTS);
     SlotRead tu = ld_slot_live(S, u);
     SlotRead tv = ld_slot_live(S, v);
-    uint32_t step = 0;
+    Link lu, lv;
+    uint32_t step = 0, desc = 0;
     for (; step < cap; ++step) {
         const uint32_t u1 = hi32(tu.w), su = lo32(tu.w), v1 = hi32(tv.w), sv = lo32(tv.w);
         if (u1 >= M || v1 >= M || su >= n || sv >= n) { err |= ST_CORRUPT; break; }
-        if (u1 != u && saddle_key(tu, f, flip) < ks) {
-            tc.add(C_GM_DESCENTS);
-            u = u1; tu = ld_slot_live(S, u); continue;
+        if (u1 != u) {
+            const uint64_t ku = saddle_key(tu, f, flip);
+            if (ku < ks) {
+                tc.add(C_GM_DESCENTS);
+                compress(S, lu, u, ku, u1, ++desc, tc);
+                lu.x = u; lu.w = tu.w; lu.k = ku;
+                u = u1; tu = ld_slot_live(S, u); continue;
+            }
         }
-        if (v1 != v && saddle_key(tv, f, flip) < ks) {
-            tc.add(C_GM_DESCENTS);
-            v = v1; tv = ld_slot_live(S, v); continue;
+        if (v1 != v) {
+            const uint64_t kv = saddle_key(tv, f, flip);
+            if (kv < ks) {
+                tc.add(C_GM_DESCENTS);
+                compress(S, lv, v, kv, v1, ++desc, tc);
+                lv.x = v; lv.w = tv.w; lv.k = kv;
+                v = v1; tv = ld_slot_live(S, v); continue;
+            }
         }
         if (u == v) break;
         if (mkey[v] < mkey[u]) {  // the upper minimum is re-pointed
             const uint32_t w = u; u = v; v = w;
             const SlotRead tw = tu; tu = tv; tv = tw;
+            const Link lw = lu; lu = lv; lv = lw;
         }
         uint64_t seen = tv.w;
         tc.add(C_GM_CAS);
@@ -868,6 +910,7 @@ __device__ void gmerge(Slot *__restrict__ S, const uint64_t *__restrict__ mkey, 
             ks = kv;
             v = hi32(tv.w);
             tv = ld_slot_live(S, v);
+            lv.x = 0xffffffffu;
         } else {
             tc.add(C_GM_CAS_FAIL);
             tv.w = seen;
@@ -1209,11 +1252,13 @@ __global__ __launch_bounds__(kBlock) void k_merge_q(const float *__restrict__ f,
 
 // Representative: follow the slots from x while the saddle is at or below
 // `level` and x is no root; the last minimum reached.
+template <bool CNT>
 __device__ __forceinline__ uint32_t chase(Slot *__restrict__ S, const float *__restrict__ f, uint32_t flip,
                                           uint32_t M, uint32_t n, uint32_t x, uint64_t level, uint32_t cap,
-                                          uint32_t &err)
+                                          uint32_t &err, Tally<CNT> &tc)
 {
     for (uint32_t step = 0; step < cap; ++step) {
+        tc.add(C_MIN_CHASES);
         const SlotRead t = ld_slot_live(S, x);
         const uint32_t v = hi32(t.w), s = lo32(t.w);
         if (v >= M || s >= n) { err |= ST_CORRUPT; return x; }
@@ -1225,21 +1270,24 @@ __device__ __forceinline__ uint32_t chase(Slot *__restrict__ S, const float *__r
     return x;
 }
 
+template <bool CNT>
 __global__ __launch_bounds__(kBlock) void k_repair_min(const float *__restrict__ f, Slot *__restrict__ S, uint32_t n,
                                                        uint32_t cap, uint32_t flip, Header *__restrict__ h)
 {
     const uint32_t M = h->n_minima;
     uint32_t err = 0;
+    Tally<CNT> tc;
     for (int64_t mm = (int64_t)blockIdx.x * kBlock + threadIdx.x; mm < M; mm += (int64_t)gridDim.x * kBlock) {
         const uint32_t m = (uint32_t)mm;
         const SlotRead t = ld_slot_live(S, m);
         const uint32_t v = hi32(t.w), s = lo32(t.w);
         if (v == m) continue;
         if (v >= M || s >= n) { err |= ST_CORRUPT; continue; }
-        const uint32_t r = chase(S, f, flip, M, n, v, saddle_key(t, f, flip), cap, err);
+        const uint32_t r = chase<CNT>(S, f, flip, M, n, v, saddle_key(t, f, flip), cap, err, tc);
         if (r != v) st_relaxed(&S[m].w, pack(s, r));
     }
     if (err) atomicOr(&h->status, err);
+    tc.flush(h);
 }
 
 // Output triplets in vertex order, field-local ids.  A local minimum copies

@@ -40,7 +40,7 @@ EXPORTS = [
 COUNTER_NAMES = [
     "gm_facts", "gm_steps", "gm_descents", "gm_cas", "gm_cas_fail", "gm_remerge", "gm_max_steps",
     "lds_merges", "lds_steps", "lds_cas", "lds_cas_fail", "lds_max_steps",
-    "table_inserts", "table_probes", "table_direct", "output_chase_steps",
+    "table_inserts", "table_probes", "table_direct", "output_chase_steps", "gm_compress", "min_chase_steps",
 ]
 
 # tree kinds (include/mt.h)

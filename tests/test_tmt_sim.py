@@ -89,3 +89,20 @@ def test_two_level_boxes(box, variant):
         for seed in range(4):
             got = tmt_sim.simulate(f, seed=seed, variant=variant, box=box)
             assert np.array_equal(got, want), (variant, box, i, seed)
+
+
+@pytest.mark.parametrize("variant", ["paper", "basins", "tile_trees_lowest"])
+@pytest.mark.parametrize("compress_after", [0, 2])
+def test_path_compression_in_descents(variant, compress_after):
+    """Merges that re-point a link they descend through (x -> y -> z with y's
+    saddle not above x's becomes x -> z at x's saddle, by compare-and-swap)
+    reach the oracle's tree under every interleaving: the early write is one
+    step of Repair (Alg. 4, 5) and leaves every connection Merge relies on."""
+    fs = _fields_tiny() + [fields.serpentine((6, 7, 8), 3), fields.serpentine((9, 10), 4, descending=True),
+                           fields.plateau_jump((6, 5, 4), 5)]
+    for i, f in enumerate(fs):
+        want = oracle.merge_tree(f)
+        for seed in range(10):
+            got = tmt_sim.simulate(f, seed=77 * i + seed, variant=variant, compress_after=compress_after,
+                                   box=(3, 2, 2))
+            assert np.array_equal(got, want), (variant, compress_after, i, seed)

@@ -45,6 +45,9 @@ Variants used by the GPU design, each checked to give the same unique T:
   basins only the one with the lowest upper end is merged (inside a box, and
   across each box face): a connection at a lower level implies the same
   connection at every higher one, so the others add nothing.
+
+Any variant can also run its merges with path compression in the descents
+(``compress_after``, see merge_thread).
 """
 from __future__ import annotations
 
@@ -90,20 +93,47 @@ def neighbours(shape):
 
 # -- threads ---------------------------------------------------------------
 
-def merge_thread(T, key, u, s, v, root_guard=True, skip_root_remerge=True, cap=100000):
-    """Alg. 3 as a loop (its recursion is a tail call), yielding before each T access."""
+def merge_thread(T, key, u, s, v, root_guard=True, skip_root_remerge=True, cap=100000, compress_after=None):
+    """Alg. 3 as a loop (its recursion is a tail call), yielding before each T access.
+
+    compress_after (None: off) adds path compression to the descents once the
+    merge has taken that many descent steps: when a descent passes x -> y (at
+    saddle sx) and then y -> z at a saddle sy not above sx, x is re-pointed
+    at z at its own saddle by a compare-and-swap, (sx, y) -> (sx, z).  x and z
+    are connected at the level of sx through y, and z lies below y, so this is
+    one step of Repair's chase (Alg. 4) written back early; a swap that finds
+    x changed does nothing.
+    """
     ks = key(s)
+    prev = [None, None]  # per side: (x, sx, y) of the link just followed
+    steps = 0
     for _ in range(cap):
         yield
         su, u1 = T[u]
         u_root = (u1 == u) and (su == u)
         if (not u_root or not root_guard) and key(su) < ks:
+            steps += 1
+            if compress_after is not None and steps > compress_after and prev[0] is not None:
+                x, sx, y = prev[0]
+                if y == u and key(su) <= key(sx):
+                    yield
+                    if T[x] == (sx, y):
+                        T[x] = (sx, u1)
+            prev[0] = (u, su, u1)
             u = u1
             continue
         yield
         sv, v1 = T[v]
         v_root = (v1 == v) and (sv == v)
         if (not v_root or not root_guard) and key(sv) < ks:
+            steps += 1
+            if compress_after is not None and steps > compress_after and prev[1] is not None:
+                x, sx, y = prev[1]
+                if y == v and key(sv) <= key(sx):
+                    yield
+                    if T[x] == (sx, y):
+                        T[x] = (sx, v1)
+            prev[1] = (v, sv, v1)
             v = v1
             continue
         if u == v:
@@ -111,6 +141,7 @@ def merge_thread(T, key, u, s, v, root_guard=True, skip_root_remerge=True, cap=1
         if key(v) < key(u):
             u, v = v, u
             su, u1, sv, v1 = sv, v1, su, u1
+            prev = [prev[1], prev[0]]
         yield
         if T[v] == (sv, v1):  # CAS, atomic in one scheduler step
             T[v] = (s, u)
@@ -118,6 +149,7 @@ def merge_thread(T, key, u, s, v, root_guard=True, skip_root_remerge=True, cap=1
                 return
             s, v = sv, v1
             ks = key(s)
+            prev[1] = None
         # CAS failed: start again with the same (u, s, v)
     raise LivelockError("merge exceeded step cap")
 
@@ -188,7 +220,7 @@ def _box_of(shape, box):
 
 
 def simulate(f, seed=0, variant="paper", edge_order=None, serial=False,
-             root_guard=True, skip_root_remerge=True, return_last=True, box=(2, 2, 2)):
+             root_guard=True, skip_root_remerge=True, return_last=True, box=(2, 2, 2), compress_after=None):
     """Run Alg. 1 (or a variant) under one seeded interleaving; returns T [N, 2]."""
     f = np.asarray(f)
     shape = f.shape
@@ -251,7 +283,8 @@ def simulate(f, seed=0, variant="paper", edge_order=None, serial=False,
         boxes = list(local.items())
         rng.shuffle(boxes)
         for bidx, ms in boxes:
-            th = [merge_thread(T, key, u, s_, v, root_guard, skip_root_remerge) for (u, s_, v) in ms]
+            th = [merge_thread(T, key, u, s_, v, root_guard, skip_root_remerge, compress_after=compress_after)
+                  for (u, s_, v) in ms]
             run_phase(th, rng)
             mins = [u for u in range(N) if zl[u] == u and bx[u] == bidx]
             run_phase([repair_thread(T, key, u, return_last) for u in mins], rng)
@@ -297,7 +330,8 @@ def simulate(f, seed=0, variant="paper", edge_order=None, serial=False,
                 boxes = list(local.items())
                 rng.shuffle(boxes)
                 for bidx, ms in boxes:
-                    th = [merge_thread(T, key, u, s_, v, root_guard, skip_root_remerge) for (u, s_, v) in ms]
+                    th = [merge_thread(T, key, u, s_, v, root_guard, skip_root_remerge, compress_after=compress_after)
+                  for (u, s_, v) in ms]
                     run_phase(th, rng)
                     mins = [u for u in range(N) if z[u] == u and bx[u] == bidx]
                     run_phase([repair_thread(T, key, u, return_last) for u in mins], rng)
@@ -305,7 +339,8 @@ def simulate(f, seed=0, variant="paper", edge_order=None, serial=False,
         raise ValueError(variant)
 
     def mk_merges():
-        return [merge_thread(T, key, u, s, v, root_guard, skip_root_remerge) for (u, s, v) in merges]
+        return [merge_thread(T, key, u, s, v, root_guard, skip_root_remerge, compress_after=compress_after)
+                for (u, s, v) in merges]
 
     if serial:
         for th in mk_merges():
