@@ -591,6 +591,12 @@ def summarize_profiles(trace_dir: str, fetch_dir: str, write_dir: str, workload:
     print(out, TRAFFIC_FILE)
 
 
+def progress(msg: str):
+    """One line on stderr when a phase of the run ends (the JSON line stays
+    alone on stdout)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -622,6 +628,7 @@ def main():
     lib = mt.load_library()
     dev = torch.device("cuda:0")
     f = fields.workload(args.workload)[0]
+    progress(f"field {args.workload} {list(f.shape)} generated")
     ft = torch.from_numpy(f).to(dev)
     s = Single(ft, lib, mt)
     for _ in range(args.warmup):
@@ -637,6 +644,7 @@ def main():
     t1 = time.perf_counter()
     dt = (t1 - t0) / args.steps
     N = s.N
+    progress(f"timed {args.steps} steps: {dt * 1e3:.3f} ms per step")
 
     # per-kernel times in a separate pass (HIP events around every launch)
     mt.profile_begin()
@@ -719,6 +727,7 @@ def main():
         del src, dst
     if not args.no_secondary:
         out["ceilings"], out["atomics"] = atomic_rates(s, mt, kstats, dev)
+        progress("ceilings and atomic rates")
         if dom in out["atomics"]:
             roofline["atomic"] = out["atomics"][dom]
     T_host = s.T.cpu().numpy().view(np.uint32).reshape(-1, 2)
@@ -727,15 +736,21 @@ def main():
     if not args.no_secondary:
         sec = {}
         sec["split_tree"] = bench_split(ft, lib, mt, s)
+        progress("split_tree")
         sec["rank_keys"] = bench_ranks(ft, lib, mt, dt * 1e3)
+        progress("rank_keys")
         del s
         torch.cuda.empty_cache()
         sec["batched"] = bench_batch(dev, mt, lib)
+        progress("batched")
         sec["backward"] = bench_backward(dev, mt)
+        progress("backward")
         sec["adversarial"] = bench_adversarial(dev, mt, lib)
+        progress("adversarial")
         out["secondary"] = sec
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(f, T_host, b_host, d_host)
+        progress("cpu baseline")
     print(json.dumps(out), flush=True)
 
 
