@@ -212,6 +212,14 @@ def cpu_baseline(f: np.ndarray, T_gpu: np.ndarray, birth_gpu: np.ndarray, death_
     }
 
 
+def tiles_of(s, mt) -> int:
+    """Tiles of the single field under the active tile shape of its dims class."""
+    nx, ny, nz = s.dims
+    cls = 0 if nz > 1 else (1 if ny > 1 else 2)
+    sh = {t["id"]: t for t in mt.tile_shapes()}[mt.get_tile_shape(cls)]
+    return -(-nx // sh["tx"]) * -(-ny // sh["ty"]) * -(-nz // sh["tz"])
+
+
 def atomic_rates(s, mt, kstats, dev):
     """Compare-and-swap rates of the merge kernels against the measured
     ceilings: one counting build of the timed field (outside the timed
@@ -231,7 +239,20 @@ def atomic_rates(s, mt, kstats, dev):
     def avg_s(k):
         return kstats[k][0] / kstats[k][1] / 1e3 if k in kstats else None
 
-    out = {"counts": c}
+    out = {"counts": {k: v for k, v in c.items() if not k.startswith("cyc_")}}
+    # phase clocks of the tile pass (a build whose tile pass only clocks its
+    # phases): share of its time per phase, workgroup-first-lane clock summed over tiles
+    mt.set_counting(2)
+    try:
+        s.build_stats()
+        cp = mt.read_counters(s.ws)
+    finally:
+        mt.set_counting(False)
+    cyc = {k[4:]: v for k, v in cp.items() if k.startswith("cyc_")}
+    tot = sum(cyc.values())
+    if tot:
+        out["k_local_phase_share"] = {k: v / tot for k, v in cyc.items()}
+        out["k_local_phase_cycles_per_tile"] = tot / max(1, tiles_of(s, mt))
     t = avg_s("k_merge_q")
     if t:
         rate = c["gm_cas"] / t / 1e9
@@ -345,12 +366,14 @@ def bench_batch(dev, mt, lib, reps: int = 5):
     # autotuned tile shapes (timed by the library, bit-identity checked on
     # the device), then the batch again with them; defaults restored after
     saved = [mt.get_tile_shape(c) for c in range(3)]
+    saved_sched = mt.get_schedule()
     saved_cache = os.environ.get("MT_AUTOTUNE_CACHE")
     os.environ["MT_AUTOTUNE_CACHE"] = os.path.join("/tmp", f"mt_autotune_bench_{os.getpid()}.json")
     try:
         tensors = [plan.fields[plan.vertex_offsets[i]:plan.vertex_offsets[i + 1]].view(shapes[i])
                    for i in range(len(shapes))]
         chosen = tune.tune(tensors, reps=3, force=True)
+        sched = tune.tune_schedule(tensors, reps=3, force=True)
         tplan = mt.BatchPlan(shapes, dev)
         tplan.fields.copy_(plan.fields)
         tt_med, _ = time_batch(tplan)
@@ -359,11 +382,14 @@ def bench_batch(dev, mt, lib, reps: int = 5):
         out["tuned"] = {"shapes": {k: [info[v]["tx"], info[v]["ty"], info[v]["tz"]] for k, v in chosen.items()},
                         "default_shapes": {tune.CLASS_NAMES[c]: [info[saved[c]]["tx"], info[saved[c]]["ty"],
                                                                  info[saved[c]]["tz"]] for c in range(3)},
+                        "schedule": sched,
+                        "default_schedule": {"xcd_remap": saved_sched[0], "merge_groups": saved_sched[1]},
                         "batched_ms": tt_med * 1e3, "over_default": tb_med / tt_med, "equals_default": same_t}
         del tplan
     finally:
         for c in range(3):
             mt.set_tile_shape(c, saved[c])
+        mt.set_schedule(*saved_sched)
         if saved_cache is None:
             os.environ.pop("MT_AUTOTUNE_CACHE", None)
         else:

@@ -323,6 +323,30 @@ int mt_autotune(const float *fields, const int64_t *dims, int32_t n_fields, uint
                 double *best_ms);
 
 /*
+ * Launch schedule and its tuner.  Two settings change how the work is laid
+ * onto the chip but never the output: the XCD-aware tile order (consecutive
+ * tiles to one XCD, so neighbouring tiles share an L2; on by default) and
+ * the workgroups per XCD of the fact scatter and the cross-tile merge (2048
+ * by default).  Both are process-wide, read when a call plans its launches,
+ * and part of the batch graph cache key.
+ *
+ * mt_set_schedule: xcd_remap 1 on, 0 off, -1 the default; merge_groups
+ * 1..65536, 0 the default; anything else MT_ERR_INVALID_ARG.
+ * mt_get_schedule writes the settings in force (either pointer may be NULL).
+ * mt_autotune_schedule times the build of the given batch (arguments as for
+ * mt_autotune; workspace of mt_batch_workspace_bytes(dims, n_fields) bytes)
+ * under every pairing of remap {on, off} with merge_groups {256, 1024, 2048,
+ * 8192}, with the current tile shapes, checks that every candidate writes
+ * bit-identical triplets (else MT_ERR_INTERNAL), selects the fastest and
+ * writes its time per build to *best_ms (host, may be NULL).  Synchronizes.
+ */
+int mt_set_schedule(int xcd_remap, int merge_groups);
+int mt_get_schedule(int *xcd_remap, int *merge_groups);
+int mt_autotune_schedule(const float *fields, const int64_t *dims, int32_t n_fields, uint32_t *triplets,
+                         uint32_t *triplets_check, void *workspace, size_t ws_bytes, int reps, void *stream,
+                         double *best_ms);
+
+/*
  * Bounds of the build's loops, for tests of its failure handling and for
  * tuning.  Both settings are process-wide and are read when a call plans its
  * launches (a batch graph captured under one setting keeps it; the setting is
@@ -342,8 +366,9 @@ int mt_autotune(const float *fields, const int64_t *dims, int32_t n_fields, uint
  * tile face) before it takes the path that needs no table: merged directly
  * inside the tile, queued as it is across tiles.  Both paths give the same
  * triplets; the tables only save merges.  probes = -1 restores the default
- * (32); 0 <= probes <= 64 sets it (0 sends every edge down the direct path);
- * anything else is MT_ERR_INVALID_ARG.  mt_get_table_probes returns it.
+ * (32, also the largest value); 0 <= probes <= 32 sets it (0 sends every
+ * edge down the direct path); anything else is MT_ERR_INVALID_ARG.
+ * mt_get_table_probes returns it.
  */
 int mt_set_max_steps(int64_t steps);
 int64_t mt_get_max_steps(void);
@@ -355,13 +380,16 @@ int mt_get_table_probes(void);
  * call (and newly captured batch graph: the flag is part of its cache key)
  * launch the counting instantiation of the merge kernels, which tally events
  * per lane and add them to counters in the workspace head with one atomic per
- * wave; mt_set_counting(0) (the default) goes back to the timed kernels, in
- * which every count is compiled out.  The triplets are the same either way.
- * mt_get_counting returns the flag.
+ * wave; mt_set_counting(2) launches instead a tile pass that only clocks its
+ * phases (counters 18-27; the per-lane event tallies would slow the phases
+ * they time), with the timed instantiation of every other kernel;
+ * mt_set_counting(0) (the default) goes back to the timed kernels, in which
+ * every count is compiled out.  The triplets are the same in every mode.
+ * mt_get_counting returns the mode; any other value is MT_ERR_INVALID_ARG.
  *
  * mt_read_counters synchronizes `stream` and copies the counters of the last
  * build on `workspace` into counts (host, uint64[n]); it returns how many it
- * wrote (at most 18; the rest of counts is zeroed) or an error.  In order:
+ * wrote (at most 28; the rest of counts is zeroed) or an error.  In order:
  *   0 cross-tile merges started (one per queued fact)
  *   1 iterations of the cross-tile merge loop (Alg. 3)
  *   2 of those, descent steps
@@ -381,6 +409,14 @@ int mt_get_table_probes(void);
  *  16 path compressions in long cross-tile descents (a link re-pointed past
  *     the next one when that one's saddle is not higher, one Repair step)
  *  17 chase steps of the minimum repair (Alg. 5 for every local minimum)
+ *  18-27 (mode 2 only) shader clock cycles of the tile pass's phases,
+ *     summed over tiles, each taken by the workgroup's first lane from one
+ *     barrier to the next
+ *     (so a phase includes the wait for its slowest wave): field loads;
+ *     lowest lower neighbours; numbering of the local minima; descent chains
+ *     to the local minima; clearing the pair table; edges offered to the
+ *     table; compaction of the table; the in-tile merges; repair of the
+ *     local minima; minimum records and vertex labels
  * Only a counting build writes them; after a timed build they read 0.
  */
 int mt_set_counting(int on);

@@ -70,7 +70,7 @@ static void with_shape(int id, F &&fn)
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t D, tfield, tstart, cs, pcnt, lbl, slot, mkey, queue, qbin, qhist, qtot, xface, total;
+    size_t D, tfield, tstart, cs, pcnt, lbl, slot, mkey, queue, qbin, qhist, qtot, xface, stage, bcnt, total;
 };
 
 struct ClassLaunch {
@@ -87,6 +87,7 @@ struct Plan {
     Layout lay{};
     // configuration in force when the plan was made
     int remap = 1;
+    int mgroups = 2048;  // workgroups per XCD of the fact scatter and the cross-tile merge
     uint32_t cap = 0, probes = 0;
     int count = 0;
 };
@@ -95,8 +96,10 @@ struct Plan {
 static std::mutex g_cfg_mu;
 static int g_shape[3] = {4, 6, 10};  // 16x16x16, 64x16, 1024
 static int g_remap = 1;
+constexpr int kDefaultMergeGroups = 2048;
+static int g_mgroups = kDefaultMergeGroups;
 constexpr uint32_t kDefaultCap = 1u << 24;
-constexpr uint32_t kDefaultProbes = 32;
+constexpr uint32_t kDefaultProbes = kMaxProbes;
 static uint32_t g_cap = kDefaultCap;
 static uint32_t g_probes = kDefaultProbes;
 static int g_count = 0;  // counting build (event counters) instead of the timed one
@@ -146,6 +149,7 @@ static int make_plan(const int64_t *dims, int32_t nf, Plan &p, const int *shape_
         read_env_locked();
         for (int c = 0; c < 3; ++c) shape[c] = shape_override ? shape_override[c] : g_shape[c];
         p.remap = g_remap;
+        p.mgroups = g_mgroups;
         p.cap = g_cap;
         p.probes = g_probes;
         p.count = g_count;
@@ -219,6 +223,8 @@ static int make_plan(const int64_t *dims, int32_t nf, Plan &p, const int *shape_
     L.qhist = o; o = align256(o + sizeof(uint32_t) * kQCounters * 8);
     L.qtot = o; o = align256(o + sizeof(uint32_t) * kQScanBlocks * 8);
     L.xface = o; o = align256(o + sizeof(uint64_t) * 2 * kXFace * p.n_tiles);
+    L.stage = o; o = align256(o + sizeof(uint4) * (size_t)kStagePerChunk * chunks);
+    L.bcnt = o; o = align256(o + (size_t)kBuckets * chunks);
     L.total = o;
     return MT_OK;
 }
@@ -234,6 +240,8 @@ struct Ptrs {
     Fact *queue, *qbin;
     uint32_t *qhist, *qtot;
     uint64_t *xface;
+    uint4 *stage;
+    uint8_t *bcnt;
 };
 
 static Ptrs ws_ptrs(const Plan &p, void *ws)
@@ -255,6 +263,8 @@ static Ptrs ws_ptrs(const Plan &p, void *ws)
     w.qhist = (uint32_t *)(b + L.qhist);
     w.qtot = (uint32_t *)(b + L.qtot);
     w.xface = (uint64_t *)(b + L.xface);
+    w.stage = (uint4 *)(b + L.stage);
+    w.bcnt = (uint8_t *)(b + L.bcnt);
     return w;
 }
 
@@ -341,11 +351,11 @@ static int enqueue_setup(const Plan &p, const Ptrs &w, uint32_t clear_status, bo
     return MT_OK;
 }
 
-template <class S, bool CNT>
+template <class S, int MODE>
 static int launch_local_as(const Plan &p, const ClassLaunch &cl, const Ptrs &w, const float *f, uint32_t flip,
                            hipStream_t st)
 {
-    auto *const kern = &k_local<S, CNT>;
+    auto *const kern = &k_local<S, MODE>;
     MT_LAUNCH("k_local", kern, dim3((unsigned)cl.ntiles), dim3(S::NT), st, f, w.lbl,
               w.slot, w.mkey, (const FieldDesc *)w.D, (const int32_t *)w.tfield + cl.cb,
               (const int64_t *)w.tstart + cl.cb, cl.nfc, cl.tile0, cl.ntiles, p.remap, (uint32_t)p.m_cap, p.cap,
@@ -357,7 +367,8 @@ template <class S>
 static int launch_local(const Plan &p, const ClassLaunch &cl, const Ptrs &w, const float *f, uint32_t flip,
                         hipStream_t st)
 {
-    return p.count ? launch_local_as<S, true>(p, cl, w, f, flip, st) : launch_local_as<S, false>(p, cl, w, f, flip, st);
+    if (p.count == 2) return launch_local_as<S, 2>(p, cl, w, f, flip, st);
+    return p.count ? launch_local_as<S, 1>(p, cl, w, f, flip, st) : launch_local_as<S, 0>(p, cl, w, f, flip, st);
 }
 
 template <class S>
@@ -372,9 +383,10 @@ static int launch_cross(const Plan &p, const ClassLaunch &cl, const Ptrs &w, con
 }
 
 // The merge tree: triplets T (field-local ids; uint32 pairs, or uint64 pairs
-// when wide) and, per chunk, pair counts.
+// when wide) and, per chunk, pair counts; with stage_pairs also the pairs
+// themselves, staged per chunk for the readout that follows.
 static int enqueue_build(const Plan &p, const Ptrs &w, const float *f, void *T, uint32_t flip, hipStream_t st,
-                         bool wide = false)
+                         bool wide = false, bool stage_pairs = false)
 {
     const int nf = (int)p.d.size();
     const uint32_t n = (uint32_t)p.n_total;
@@ -395,21 +407,22 @@ static int enqueue_build(const Plan &p, const Ptrs &w, const float *f, void *T, 
         if (rc != MT_OK) return rc;
     }
     // facts into ascending order of their saddle's key bin, per XCD queue
-    const unsigned gq = 8 * (unsigned)std::min<int64_t>(2048, std::max<int64_t>(1, (p.q_cap + kBlock - 1) / kBlock));
+    const unsigned gq =
+        8 * (unsigned)std::min<int64_t>(p.mgroups, std::max<int64_t>(1, (p.q_cap + kBlock - 1) / kBlock));
     MT_LAUNCH("k_qtotals", k_qtotals, dim3(kQScanBlocks, 8), dim3(kQScanThreads), st, (const uint32_t *)w.qhist,
               w.qtot);
     MT_LAUNCH("k_qscan", k_qscan, dim3(kQScanBlocks, 8), dim3(kQScanThreads), st, w.qhist,
               (const uint32_t *)w.qtot);
     MT_LAUNCH("k_qscatter", k_qscatter, dim3(gq), dim3(kBlock), st, (const Fact *)w.queue, w.qbin,
               (uint32_t)p.q_cap, w.qhist, w.h);
-    if (p.count)
+    if (p.count == 1)
         MT_LAUNCH("k_merge_q", k_merge_q<true>, dim3(gq), dim3(kBlock), st, f, (const Fact *)w.qbin,
                   (uint32_t)p.q_cap, w.slot, (const uint64_t *)w.mkey, n, p.cap, flip, w.h);
     else
         MT_LAUNCH("k_merge_q", k_merge_q<false>, dim3(gq), dim3(kBlock), st, f, (const Fact *)w.qbin,
                   (uint32_t)p.q_cap, w.slot, (const uint64_t *)w.mkey, n, p.cap, flip, w.h);
     const unsigned gm = (unsigned)std::min<int64_t>(8192, std::max<int64_t>(1, (p.m_cap + kBlock - 1) / kBlock));
-    if (p.count)
+    if (p.count == 1)
         MT_LAUNCH("k_repair_min", k_repair_min<true>, dim3(gm), dim3(kBlock), st, f, w.slot, n, p.cap, flip, w.h);
     else
         MT_LAUNCH("k_repair_min", k_repair_min<false>, dim3(gm), dim3(kBlock), st, f, w.slot, n, p.cap, flip, w.h);
@@ -417,14 +430,15 @@ static int enqueue_build(const Plan &p, const Ptrs &w, const float *f, void *T, 
         using O = decltype(out);
         auto *const kern = &k_repair_reg<decltype(cnt)::value, O>;
         MT_LAUNCH("k_repair_reg", kern, dim3((unsigned)p.n_chunks), dim3(kBlock), st, f, (const uint32_t *)w.lbl,
-                  w.slot, (const uint64_t *)w.mkey, (typename O::Word *)T, w.pcnt, (const FieldDesc *)w.D,
+                  w.slot, (const uint64_t *)w.mkey, (typename O::Word *)T, w.pcnt,
+                  stage_pairs ? w.stage : nullptr, stage_pairs ? w.bcnt : nullptr, (const FieldDesc *)w.D,
                   (const int64_t *)w.cs, nf, n, p.cap, flip, w.h);
         return MT_OK;
     };
     using CT = std::true_type;
     using CF = std::false_type;
-    if (wide) return p.count ? reg(CT{}, Out64{}) : reg(CF{}, Out64{});
-    return p.count ? reg(CT{}, Out32{}) : reg(CF{}, Out32{});
+    if (wide) return p.count == 1 ? reg(CT{}, Out64{}) : reg(CF{}, Out64{});
+    return p.count == 1 ? reg(CT{}, Out32{}) : reg(CF{}, Out32{});
 }
 
 template <class O>
@@ -444,7 +458,8 @@ static int enqueue_pairs_as(const Plan &p, const Ptrs &w, bool after_build, cons
     auto *const kw = &k_pairs_write<O>;
     MT_LAUNCH("k_pairs_write", kw, dim3((unsigned)p.n_chunks), dim3(kBlock), st, f, T, (const FieldDesc *)w.D,
               (const int64_t *)w.cs, nf, (const uint32_t *)w.pcnt, capacity, (typename O::Id *)birth,
-              (typename O::Id *)death, bval, dval);
+              (typename O::Id *)death, bval, dval, after_build ? (const uint4 *)w.stage : nullptr,
+              after_build ? (const uint8_t *)w.bcnt : nullptr);
     return MT_OK;
 }
 
@@ -616,7 +631,7 @@ static int build_pairs(const float *field, int64_t nx, int64_t ny, int64_t nz, i
     hipStream_t st = (hipStream_t)stream;
     const Ptrs w = ws_ptrs(p, workspace);
     if ((rc = enqueue_setup(p, w, ~0u, true, st)) != MT_OK) return rc;
-    if ((rc = enqueue_build(p, w, field, triplets, kind_flip(kind), st, wide)) != MT_OK) return rc;
+    if ((rc = enqueue_build(p, w, field, triplets, kind_flip(kind), st, wide, true)) != MT_OK) return rc;
     rc = enqueue_pairs(p, w, true, field, triplets, capacity, birth, death, birth_val, death_val, nullptr, st, wide);
     if (rc != MT_OK) return rc;
     Header h;
@@ -669,9 +684,10 @@ int mt_batch_build_tree(const float *fields, const int64_t *dims, int32_t n_fiel
     std::string key;
     key.reserve(96 + 24 * n_fields);
     char buf[320];
-    snprintf(buf, sizeof buf, "%d|%d|%p|%p|%p|%p|%p|%p|%lld|%p|%p|%zu|%d|%u|%u|%d|%d,%d,%d", dev, kind,
+    snprintf(buf, sizeof buf, "%d|%d|%p|%p|%p|%p|%p|%p|%lld|%p|%p|%zu|%d|%d|%u|%u|%d|%d,%d,%d", dev, kind,
              (const void *)fields, (void *)triplets, (void *)birth, (void *)death, (void *)birth_val,
-             (void *)death_val, (long long)pair_capacity, (void *)pair_offsets, workspace, ws_bytes, p.remap, p.cap,
+             (void *)death_val, (long long)pair_capacity, (void *)pair_offsets, workspace, ws_bytes, p.remap,
+             p.mgroups, p.cap,
              p.probes, p.count, p.cls[0].shape, p.cls[1].shape, p.cls[2].shape);
     key += buf;
     for (const FieldDesc &d : p.d) {
@@ -687,7 +703,7 @@ int mt_batch_build_tree(const float *fields, const int64_t *dims, int32_t n_fiel
         const Ptrs w = ws_ptrs(p, workspace);
         if (hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed) != hipSuccess) return MT_ERR_HIP;
         int rc1 = enqueue_setup(p, w, ~0u, true, cs);
-        if (rc1 == MT_OK) rc1 = enqueue_build(p, w, fields, (uint64_t *)triplets, kind_flip(kind), cs);
+        if (rc1 == MT_OK) rc1 = enqueue_build(p, w, fields, (uint64_t *)triplets, kind_flip(kind), cs, false, true);
         if (rc1 == MT_OK)
             rc1 = enqueue_pairs(p, w, true, fields, (const uint64_t *)triplets, pair_capacity, birth, death,
                                 birth_val, death_val, pair_offsets, cs);
@@ -829,7 +845,7 @@ int64_t mt_get_max_steps(void)
 
 int mt_set_table_probes(int probes)
 {
-    if (probes < -1 || probes > 64) return MT_ERR_INVALID_ARG;
+    if (probes < -1 || probes > kMaxProbes) return MT_ERR_INVALID_ARG;
     std::lock_guard<std::mutex> lk(g_cfg_mu);
     read_env_locked();
     g_probes = probes < 0 ? kDefaultProbes : (uint32_t)probes;
@@ -845,7 +861,7 @@ int mt_get_table_probes(void)
 
 int mt_set_counting(int on)
 {
-    if (on != 0 && on != 1) return MT_ERR_INVALID_ARG;
+    if (on < 0 || on > 2) return MT_ERR_INVALID_ARG;
     std::lock_guard<std::mutex> lk(g_cfg_mu);
     read_env_locked();
     g_count = on;
@@ -900,6 +916,46 @@ size_t mt_autotune_workspace_bytes(const int64_t *dims, int32_t n_fields)
     return best;
 }
 
+}  // extern "C"
+
+namespace {
+// One autotuner candidate: `reps` timed builds (after one warm-up) with plan
+// p into `out`; when `ref` is not null the triplets must equal ref's bit for
+// bit (else MT_ERR_INTERNAL, latched by k_compare).  Synchronizes.
+int time_candidate(const Plan &p, void *workspace, const float *fields, uint64_t *out, const uint64_t *ref,
+                   int reps, hipStream_t st, hipEvent_t e0, hipEvent_t e1, double &ms_per_build)
+{
+    const Ptrs w = ws_ptrs(p, workspace);
+    int rc = MT_OK;
+    for (int r = -1; r < reps && rc == MT_OK; ++r) {  // r = -1: warm-up
+        if (r == 0 && hipEventRecord(e0, st) != hipSuccess) rc = MT_ERR_HIP;
+        if (rc == MT_OK) rc = enqueue_setup(p, w, ~0u, true, st);
+        if (rc == MT_OK) rc = enqueue_build(p, w, fields, out, 0u, st);
+    }
+    if (rc != MT_OK) return rc;
+    if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return MT_ERR_HIP;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return MT_ERR_HIP;
+    if (ref) {
+        hipLaunchKernelGGL(k_compare, dim3(1024), dim3(kBlock), 0, st, ref, (const uint64_t *)out, p.n_total,
+                           &w.h->status);
+        if (hipGetLastError() != hipSuccess) return MT_ERR_HIP;
+    }
+    Header h;
+    if ((rc = read_header(workspace, st, h)) != MT_OK) return rc;
+    if ((rc = status_to_code(h.status)) != MT_OK) return rc;
+    ms_per_build = (double)ms / reps;
+    return MT_OK;
+}
+
+// Candidates of the schedule tuner: XCD-aware tile order on or off, and the
+// workgroups per XCD of the fact scatter and cross-tile merge.
+constexpr int kSchedRemap[] = {1, 0};
+constexpr int kSchedGroups[] = {256, 1024, 2048, 8192};
+}  // namespace
+
+extern "C" {
+
 int mt_autotune(const float *fields, const int64_t *dims, int32_t n_fields, uint32_t *triplets,
                 uint32_t *triplets_check, void *workspace, size_t ws_bytes, int reps, void *stream,
                 double *best_ms)
@@ -929,27 +985,14 @@ int mt_autotune(const float *fields, const int64_t *dims, int32_t n_fields, uint
             Plan p;
             if ((rc = make_plan(dims, n_fields, p, sh)) != MT_OK) break;
             if (p.lay.total > ws_bytes) continue;  // does not fit the caller's workspace
-            const Ptrs w = ws_ptrs(p, workspace);
-            uint64_t *out = (uint64_t *)(have_ref ? triplets : triplets_check);
-            for (int r = -1; r < reps && rc == MT_OK; ++r) {  // r = -1: warm-up
-                if (r == 0 && hipEventRecord(e0, st) != hipSuccess) rc = MT_ERR_HIP;
-                if (rc == MT_OK) rc = enqueue_setup(p, w, ~0u, true, st);
-                if (rc == MT_OK) rc = enqueue_build(p, w, fields, out, 0u, st);
-            }
+            double t = 0.0;
+            // the first candidate writes the reference, every later one is compared with it
+            rc = time_candidate(p, workspace, fields, (uint64_t *)(have_ref ? triplets_check : triplets),
+                                have_ref ? (const uint64_t *)triplets : nullptr, reps, st, e0, e1, t);
             if (rc != MT_OK) break;
-            if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) { rc = MT_ERR_HIP; break; }
-            float ms = 0.f;
-            if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rc = MT_ERR_HIP; break; }
-            if (have_ref) {  // same triplets as the first candidate, bit for bit
-                hipLaunchKernelGGL(k_compare, dim3(1024), dim3(kBlock), 0, st, (const uint64_t *)triplets,
-                                   (const uint64_t *)triplets_check, p.n_total, &w.h->status);
-            }
-            Header h;
-            if ((rc = read_header(workspace, st, h)) != MT_OK) break;
-            if ((rc = status_to_code(h.status)) != MT_OK) break;
             have_ref = true;
-            if (ms / reps < best_t) {
-                best_t = ms / reps;
+            if (t < best_t) {
+                best_t = t;
                 best_id = id;
             }
         }
@@ -962,6 +1005,65 @@ int mt_autotune(const float *fields, const int64_t *dims, int32_t n_fields, uint
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return rc;
+}
+
+int mt_set_schedule(int xcd_remap, int merge_groups)
+{
+    if (xcd_remap < -1 || xcd_remap > 1 || merge_groups < 0 || merge_groups > 65536) return MT_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(g_cfg_mu);
+    read_env_locked();
+    g_remap = xcd_remap < 0 ? 1 : xcd_remap;
+    g_mgroups = merge_groups == 0 ? kDefaultMergeGroups : merge_groups;
+    return MT_OK;
+}
+
+int mt_get_schedule(int *xcd_remap, int *merge_groups)
+{
+    std::lock_guard<std::mutex> lk(g_cfg_mu);
+    read_env_locked();
+    if (xcd_remap) *xcd_remap = g_remap;
+    if (merge_groups) *merge_groups = g_mgroups;
+    return MT_OK;
+}
+
+int mt_autotune_schedule(const float *fields, const int64_t *dims, int32_t n_fields, uint32_t *triplets,
+                         uint32_t *triplets_check, void *workspace, size_t ws_bytes, int reps, void *stream,
+                         double *best_ms)
+{
+    if (!fields || !triplets || !triplets_check || reps < 1) return MT_ERR_INVALID_ARG;
+    if (((uintptr_t)triplets & 7u) || ((uintptr_t)triplets_check & 7u)) return MT_ERR_INVALID_ARG;
+    Plan p;
+    int rc = make_plan(dims, n_fields, p);
+    if (rc != MT_OK) return rc;
+    if ((rc = check_ws(p, workspace, ws_bytes)) != MT_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return MT_ERR_HIP;
+    int best_r = p.remap, best_g = p.mgroups;
+    double best_t = 1e300;
+    bool have_ref = false;
+    for (int r : kSchedRemap) {
+        for (int g : kSchedGroups) {
+            p.remap = r;
+            p.mgroups = g;
+            double t = 0.0;
+            rc = time_candidate(p, workspace, fields, (uint64_t *)(have_ref ? triplets_check : triplets),
+                                have_ref ? (const uint64_t *)triplets : nullptr, reps, st, e0, e1, t);
+            if (rc != MT_OK) break;
+            have_ref = true;
+            if (t < best_t) {
+                best_t = t;
+                best_r = r;
+                best_g = g;
+            }
+        }
+        if (rc != MT_OK) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != MT_OK) return rc;
+    if (best_ms) *best_ms = best_t;
+    return mt_set_schedule(best_r, best_g);
 }
 
 int mt_build_stats(const void *workspace, void *stream, int64_t *n_local_minima, int64_t *n_cross_facts)
@@ -999,7 +1101,9 @@ int mt_pairs_backward(const int64_t *dims, int32_t n_fields, const int64_t *pair
     }
     voff[n_fields] = off;
     hipStream_t st = (hipStream_t)stream;
-    if (!accumulate) MT_LAUNCH("k_fill0", k_fill0, dim3(grid1d(off)), dim3(kBlock), st, grad_field, off);
+    if (!accumulate)
+        MT_LAUNCH("k_fill0", k_fill0, dim3((unsigned)std::min<int64_t>(8192, grid1d((off + 3) / 4))), dim3(kBlock), st,
+                  grad_field, off);
     if (pair_capacity == 0) return MT_OK;
     const unsigned blocks = (unsigned)std::min<int64_t>(2048, (pair_capacity + kBlock - 1) / kBlock);
     for (int32_t first = 0; first < n_fields; first += kBwdGroup) {

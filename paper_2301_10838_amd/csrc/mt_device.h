@@ -78,6 +78,7 @@ constexpr int kXFace = 256;                  // largest x face of a tile shape (
 // such bins anyway).  Each bin's counter has kQCopies copies (chosen by the
 // fact's queue position, so the counting and the scattering pass agree),
 // which keeps the atomics on one bin apart.
+constexpr int kMaxProbes = 32;               // pair-table probes per edge, at most (and the default)
 constexpr int kQBinBits = 9;
 constexpr int kQBins = 1 << kQBinBits;
 constexpr int kQCopies = 16;
@@ -122,6 +123,19 @@ enum CtrId {
     C_REG_CHASES,     // chase steps of the output pass
     C_GM_COMPRESS,    // path compressions in cross-tile descents
     C_MIN_CHASES,     // chase steps of the minimum repair
+    // shader clock cycles of each barrier-separated phase of the tile pass,
+    // summed over tiles (taken by the workgroup's first lane, so each phase
+    // includes the wait for its slowest wave)
+    C_PH_LOAD,        // field loads, order keys into LDS
+    C_PH_DESCENT,     // lowest lower neighbour of every vertex
+    C_PH_NUMBER,      // local minima numbered, their records initialised
+    C_PH_BASIN,       // descent chains followed to the local minimum
+    C_PH_CLEAR,       // pair table cleared
+    C_PH_INSERT,      // edges between basins marked and offered to the table
+    C_PH_COMPACT,     // occupied table entries compacted
+    C_PH_MERGE,       // merges of the kept edges (Alg. 3 in LDS)
+    C_PH_REPAIR,      // repair of the local minima (Alg. 5)
+    C_PH_LABEL,       // minimum records written, vertices labelled
     kCtr
 };
 __host__ __device__ constexpr bool ctr_is_max(int i) { return i == C_GM_MAX_STEPS || i == C_LDS_MAX_STEPS; }
@@ -458,7 +472,11 @@ __device__ void lds_merge(uint64_t *TL, const uint32_t *hk, const uint16_t *mh, 
     if (step == cap) err |= ST_LIVELOCK;
 }
 
-template <class S, bool CNT>
+// MODE 0: the timed kernel; 1: counting build (event counts); 2: phase
+// clocks only (the tile pass's phases timed by the workgroup's first lane
+// into LDS, added to the counters once per workgroup; no event counts, whose
+// per-lane registers would slow the phases down).
+template <class S, int MODE>
 __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f, uint32_t *__restrict__ lbl,
                                                  Slot *__restrict__ slot, uint64_t *__restrict__ mkey,
                                                  const FieldDesc *__restrict__ D, const int32_t *__restrict__ tfield,
@@ -495,6 +513,25 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
 
     const int64_t tl = xcd_tile(blockIdx.x, gridDim.x, remap);
     if (tl >= ntiles) return;
+    constexpr bool CNT = MODE == 1;
+    Tally<CNT> tc;
+    __shared__ uint32_t phc[MODE == 2 ? kCtr : 1];  // phase clocks of this workgroup
+    uint64_t ph_t = 0;                              // clock at the end of the previous phase
+    if constexpr (MODE == 2) {
+        if (threadIdx.x == 0) {
+            for (int i = 0; i < kCtr; ++i) phc[i] = 0;
+            ph_t = clock64();
+        }
+    }
+    auto phase = [&](int id) {
+        if constexpr (MODE == 2) {
+            if (threadIdx.x == 0) {
+                const uint64_t t = clock64();
+                phc[id] += (uint32_t)(t - ph_t);
+                ph_t = t;
+            }
+        }
+    };
     const TileCtx c = tile_ctx<S>(D, tfield, tstart, nfc, tile0 + tl);
     const uint32_t off = (uint32_t)c.d.offset;
     auto valid = [&](int lx, int ly, int lz) { return lx < c.ex && ly < c.ey && lz < c.ez; };
@@ -530,6 +567,7 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
         if (__ballot(nan) != 0ull && (threadIdx.x & 63) == 0) atomicOr(&h->status, ST_NAN);
     }
     __syncthreads();
+    phase(C_PH_LOAD);
 
     // lowest lower neighbour inside the tile
 #pragma unroll
@@ -554,6 +592,7 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
         wl[p] = (int16_t)bp;
     }
     __syncthreads();
+    phase(C_PH_DESCENT);
 
     // Number the local minima in tile order (position k * NT + thread):
     // per-wave ballots, one scan of the VOL / 64 wave counts by wave 0.
@@ -606,6 +645,7 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
         }
     }
     __syncthreads();  // the basin pass reads the minima's numbers
+    phase(C_PH_NUMBER);
     const uint32_t cnt = scnt;
 
     // local basins: follow the pointers to the local minimum (keys fall
@@ -648,8 +688,10 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
             if ((moved >> k) & 1u) zl[k * NT + threadIdx.x] = zz[k];
     }
     __syncthreads();
+    phase(C_PH_BASIN);
     for (int i = threadIdx.x; i < H; i += NT) htab[i] = ~0ull;
     __syncthreads();
+    phase(C_PH_CLEAR);
 
     // Edges inside the tile whose ends lie in different local basins.  Of all
     // edges joining the same two basins only the lowest (smallest upper end)
@@ -658,7 +700,6 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
     // lowest edge; an edge that finds no table room is merged directly, and so
     // is every edge of a tile with more minima than a tag can number.
     uint32_t err = 0;
-    Tally<CNT> tc;
     const bool tabled = (uint32_t)HALF <= ZMAX || cnt <= ZMAX;
     // One atomic min per probe: an empty entry is claimed; an entry of the
     // same pair keeps the lower edge; an entry of another pair keeps the
@@ -671,7 +712,11 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
     auto insert = [&](uint64_t val) {
         tc.add(C_TAB_INSERTS);
         uint32_t si = ((uint32_t)(val & TAGM) * 0x9E3779B1u) >> (32 - PB);
-        for (uint32_t probe = 0; probe < probes; ++probe) {
+        // (a loop of compile-time length, unrolled: measurably faster than a
+        // loop to the runtime bound)
+#pragma unroll
+        for (int probe = 0; probe < kMaxProbes; ++probe) {
+            if ((uint32_t)probe >= probes) break;
             tc.add(C_TAB_PROBES);
             const uint64_t prev = __hip_atomic_fetch_min(htab + si, val, __ATOMIC_RELAXED,
                                                          __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -715,6 +760,7 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
         }
     }
     __syncthreads();
+    phase(C_PH_INSERT);
     // Occupied entries, compacted to the front of the table so that every
     // lane of a wave has a merge: each lane holds its entries while the
     // table is rewritten.
@@ -739,6 +785,7 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
             if (e[k] != ~0ull) htab[pos[k]] = e[k];
     }
     __syncthreads();
+    phase(C_PH_COMPACT);
     const uint32_t nw = nwin;
     for (uint32_t i = threadIdx.x; i < nw; i += NT) {
         const uint64_t e = htab[i];
@@ -746,6 +793,7 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
         lds_merge<VOL, CNT>(TL, hk, mh, tag & (ZMAX - 1), e >> (2 * ZB), tag >> ZB, cnt, cap, err, tc);
     }
     __syncthreads();
+    phase(C_PH_MERGE);
 
     // Repair (Alg. 5) of the local minima: target -> deepest local minimum
     // reached through links whose saddle is at or below the minimum's own.
@@ -766,6 +814,7 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
     }
     if (threadIdx.x == 63) sb0 = gbase;
     __syncthreads();
+    phase(C_PH_REPAIR);
     const uint32_t b0 = sb0;
     if (b0 + cnt > mcap || b0 + cnt < b0) {  // cannot happen: capacity bounds the minima
         if (threadIdx.x == 0) atomicOr(&h->status, ST_CORRUPT);
@@ -825,6 +874,11 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
                 xface[((size_t)c.t * 2 + (lx != 0)) * kXFace + ly + TY * lz] =
                     ((uint64_t)hk[p] << 32) | (b0 + xs[k]);
         }
+    }
+    phase(C_PH_LABEL);
+    if constexpr (MODE == 2) {
+        if (threadIdx.x == 0)
+            for (int i = C_PH_LOAD; i <= C_PH_LABEL; ++i) atomicAdd(&h->ctr[i], (unsigned long long)phc[i]);
     }
     if (err) atomicOr(&h->status, err);
     tc.flush(h);
@@ -1290,35 +1344,74 @@ __global__ __launch_bounds__(kBlock) void k_repair_min(const float *__restrict__
     tc.flush(h);
 }
 
+// Value of an order key's value part (inverse of okey, flip undone).  The
+// key folds -0.0 onto +0.0, so a key of +0.0 does not say which zero the
+// field holds: callers read the field for that one key.
+__device__ __forceinline__ uint32_t key_bits(uint32_t k, uint32_t flip)
+{
+    k ^= flip;
+    return (k & 0x80000000u) ? (k & 0x7fffffffu) : ~k;
+}
+constexpr uint32_t kKeyZero = 0x80000000u;  // okey(+0.0) == okey(-0.0)
+
+// Staged pair readout.  The output pass already knows every pair (a local
+// minimum u whose repaired triplet has s != u) together with both values
+// (f[u] from its level key, f[s] from the saddle key), so it writes them
+// out, and the readout only has to move them to their place in ascending
+// birth order instead of reading T again.  Chunk c's vertices fall into 64
+// buckets of 64 consecutive ids, bucket (group g, vertex slot i, wave w) =
+// g * 16 + i * 4 + w; each wave appends its pairs, in bucket order, to a
+// list of its own of kStageCap entries {birth, death, f[birth], f[death]}
+// (field-local ids), and records each bucket's count.  A wave with more
+// pairs than that keeps only the count, and the readout then takes the
+// chunk from T instead.
+constexpr int kStageCap = 256;                               // entries per wave and chunk
+constexpr int kBuckets = kChunk / 64;                        // 64 buckets of 64 vertices
+constexpr int kStagePerChunk = (kBlock / 64) * kStageCap;    // entries per chunk
+
 // Output triplets in vertex order, field-local ids.  A local minimum copies
 // its own (repaired) triplet; any other vertex u gets (u, u, representative
 // of its local minimum at the level of u).  Also counts pairs and roots per
-// chunk.  Slots are read-only here, so plain loads; each lane carries RV
-// vertices at once, so the dependent loads of their chases (label -> slot ->
-// slot ... -> minimum key) overlap.
+// chunk, and stages the pairs when `stage` is not null.  Slots are read-only
+// here, so plain loads; each lane carries RV vertices at once, so the
+// dependent loads of their chases (label -> slot -> slot ... -> minimum key)
+// overlap.
 constexpr int RV = 4;
+// The id half of minimum m's key word (ids are the low 32 bits): one 4-byte load.
+__device__ __forceinline__ uint32_t mkey_id(const uint64_t *__restrict__ mkey, uint32_t m)
+{
+    return reinterpret_cast<const uint32_t *>(mkey)[2 * (size_t)m];
+}
+static_assert(kChunk == kBlock * RV * 4 && (kBlock / 64) * RV * 4 == kBuckets, "bucket layout");
 template <bool CNT, class O>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_repair_reg(const float *__restrict__ f, const uint32_t *__restrict__ lbl,
                                                        const Slot *__restrict__ S, const uint64_t *__restrict__ mkey,
                                                        typename O::Word *__restrict__ T, uint32_t *__restrict__ pcnt,
+                                                       uint4 *__restrict__ stage, uint8_t *__restrict__ bcnt,
                                                        const FieldDesc *__restrict__ D, const int64_t *__restrict__ cs,
                                                        int nf, uint32_t n, uint32_t cap, uint32_t flip,
                                                        Header *__restrict__ h)
 {
-    __shared__ uint32_t sp[kBlock / 64], sr[kBlock / 64];
+    __shared__ uint32_t sp[kBlock / 64];
     const int64_t c = blockIdx.x;
+    // (the wave index is uniform: kept in a scalar register, like everything per wave below)
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    uint32_t wcnt = 0;  // pairs of the wave's vertices in this chunk (staged ones: the first kStageCap)
     const FieldDesc d = D[search(cs, nf, c)];
     const int64_t lo = (c - d.chunk_start) * kChunk;
     const int64_t hi = min(lo + (int64_t)kChunk, d.n);
     const uint32_t off = (uint32_t)d.offset;
     const uint32_t M = h->n_minima;
-    uint32_t err = 0, np = 0, nr = 0;
+    uint32_t err = 0;
     Tally<CNT> tc;
     static_assert(kChunk % (kBlock * RV) == 0, "whole groups per chunk");
     for (int64_t g0 = lo; g0 < hi; g0 += kBlock * RV) {
-        uint32_t u[RV], z[RV], x[RV], s[RV], gr[RV];
-        uint64_t level[RV], mz[RV], tw[RV], tk[RV];
-        uint32_t live = 0, act = 0, need = 0;  // bit i: vertex i is written / chasing / needs mkey[x[i]]
+        const int gi = (int)((g0 - lo) / (kBlock * RV));
+        uint32_t u[RV], z[RV], x[RV], s[RV];
+        uint64_t level[RV], tw[RV], tk[RV];
+        uint32_t mz[RV];  // id of the local minimum z (the low half of its key word)
+        // bit i: vertex i is written / chasing / gets target mkey[x[i]] (else itself: a root)
+        uint32_t live = 0, act = 0, need = 0;
 #pragma unroll
         for (int i = 0; i < RV; ++i) {
             const int64_t j = g0 + i * kBlock + threadIdx.x;
@@ -1335,7 +1428,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                 z[i] = 0;
                 live &= ~(1u << i);
             }
-            mz[i] = mkey[z[i]];
+            mz[i] = mkey_id(mkey, z[i]);
             tw[i] = S[z[i]].w;
             tk[i] = S[z[i]].k;
         }
@@ -1343,31 +1436,49 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
         for (int i = 0; i < RV; ++i) {
             x[i] = z[i];
             s[i] = u[i];
-            gr[i] = u[i];
             const uint32_t s0 = lo32(tw[i]), v0 = hi32(tw[i]);
+            bool pf = false;  // u is a pair birth (a live local minimum with s != u)
+            uint32_t dk = 0;  // then: the value key of its saddle
             if (v0 >= M || s0 >= n) {
                 if ((live >> i) & 1u) err |= ST_CORRUPT;
                 live &= ~(1u << i);
-                continue;
-            }
-            const uint64_t sk = lo32(tk[i]) == s0 ? tk[i] : vkey(f, s0, flip);
-            if (lo32(mz[i]) == u[i]) {  // u is a local minimum: its own repaired triplet
-                s[i] = s0;
-                if ((live >> i) & 1u) {
-                    np += (s0 != u[i]);
-                    nr += (v0 == z[i]);
-                }
-                if (v0 != z[i]) {
+            } else {
+                const uint64_t sk = lo32(tk[i]) == s0 ? tk[i] : vkey(f, s0, flip);
+                if (mz[i] == u[i]) {  // u is a local minimum: its own repaired triplet
+                    s[i] = s0;
+                    if ((live >> i) & 1u) {
+                        // a root: one per connected component, so counted by a rare atomic
+                        if (v0 == z[i]) atomicAdd((unsigned long long *)&h->roots, 1ull);
+                        pf = s0 != u[i];
+                        dk = hi32(sk);
+                    }
+                    if (v0 != z[i]) {
+                        x[i] = v0;
+                        need |= 1u << i;
+                    }
+                } else if (v0 == z[i] || sk > level[i]) {
+                    need |= 1u << i;  // target z itself
+                } else {                    // (u, u, representative of z at the level of u)
                     x[i] = v0;
+                    act |= 1u << i;
                     need |= 1u << i;
                 }
-            } else if (v0 == z[i] || sk > level[i]) {
-                gr[i] = lo32(mz[i]);
-            } else {                    // (u, u, representative of z at the level of u)
-                x[i] = v0;
-                act |= 1u << i;
-                need |= 1u << i;
             }
+            const uint64_t m = __ballot(pf);
+            if (stage) {  // (uniform) the pair onto the wave's list, in bucket (gi, i, wave)
+                // rank among the wave's pairs: the pairs of lower lanes, counted by mbcnt
+                const uint32_t r = wcnt + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                                   __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                if (pf && r < (uint32_t)kStageCap) {
+                    const uint32_t bk = hi32(level[i]);
+                    const uint32_t bb = bk == (kKeyZero ^ flip) ? __float_as_uint(f[u[i]]) : key_bits(bk, flip);
+                    const uint32_t db = dk == (kKeyZero ^ flip) ? __float_as_uint(f[s0]) : key_bits(dk, flip);
+                    stage[((size_t)c * (kBlock / 64) + wave) * kStageCap + r] =
+                        make_uint4(u[i] - off, s0 - off, bb, db);
+                }
+                if (lane == 0) bcnt[(size_t)c * kBuckets + gi * 16 + i * 4 + wave] = (uint8_t)__popcll(m);
+            }
+            wcnt += (uint32_t)__popcll(m);
         }
         for (uint32_t step = 0; act != 0; ++step) {
             if (step == cap) { err |= ST_LIVELOCK; break; }
@@ -1398,25 +1509,24 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
         }
 #pragma unroll
         for (int i = 0; i < RV; ++i)
-            if ((need >> i) & 1u) gr[i] = lo32(mkey[x[i]]);
+            x[i] = ((need >> i) & 1u) ? mkey_id(mkey, x[i]) : u[i];  // the target's id
 #pragma unroll
         for (int i = 0; i < RV; ++i) {
             if (!((live >> i) & 1u)) continue;
-            if (gr[i] >= n) { err |= ST_CORRUPT; continue; }
-            O::store(T, u[i], s[i] - off, gr[i] - off);
+            if (x[i] >= n) { err |= ST_CORRUPT; continue; }
+            O::store(T, u[i], s[i] - off, x[i] - off);
         }
     }
-    for (int o = 32; o > 0; o >>= 1) {
-        np += __shfl_xor(np, o);
-        nr += __shfl_xor(nr, o);
-    }
-    if ((threadIdx.x & 63) == 0) { sp[threadIdx.x >> 6] = np; sr[threadIdx.x >> 6] = nr; }
+    if (lane == 0) sp[wave] = wcnt;
+    // buckets of groups past the end of the field hold no pair
+    if (stage)
+        for (int g = (int)((hi - lo + kBlock * RV - 1) / (kBlock * RV)); g < kChunk / (kBlock * RV); ++g)
+            if (lane < RV) bcnt[(size_t)c * kBuckets + g * 16 + lane * 4 + wave] = 0;
     __syncthreads();
     if (threadIdx.x == 0) {
-        uint32_t a = 0, b = 0;
-        for (int w = 0; w < kBlock / 64; ++w) { a += sp[w]; b += sr[w]; }
+        uint32_t a = 0;
+        for (int w = 0; w < kBlock / 64; ++w) a += sp[w];
         pcnt[c] = a;
-        if (b) atomicAdd((unsigned long long *)&h->roots, (unsigned long long)b);
     }
     if (err) atomicOr(&h->status, err);
     tc.flush(h);
@@ -1567,6 +1677,12 @@ __device__ __forceinline__ uint32_t select_bit(uint64_t m, uint32_t k)
 // shares the wave totals.  Then lane k of a pass takes the wave's k-th pair
 // (its word by the word counts' prefix, its bit by halving), so the value
 // gathers and the stores run on dense lanes, 64 consecutive pairs a pass.
+//
+// When the output pass staged the chunk's pairs (stage not null, no wave of
+// the chunk past kStageCap), the pairs are instead copied from the wave lists:
+// entry e of wave w's list lies in bucket (g, i, w) where the list's bucket
+// prefix puts it, and its place in the chunk is the number of the chunk's
+// pairs in earlier buckets plus its rank inside its bucket.
 template <class O>
 __global__ __launch_bounds__(kBlock) void k_pairs_write(const float *__restrict__ f,
                                                         const typename O::Word *__restrict__ T,
@@ -1574,19 +1690,75 @@ __global__ __launch_bounds__(kBlock) void k_pairs_write(const float *__restrict_
                                                         int nf, const uint32_t *__restrict__ base, int64_t capacity,
                                                         typename O::Id *__restrict__ birth,
                                                         typename O::Id *__restrict__ death,
-                                                        float *__restrict__ bval, float *__restrict__ dval)
+                                                        float *__restrict__ bval, float *__restrict__ dval,
+                                                        const uint4 *__restrict__ stage,
+                                                        const uint8_t *__restrict__ bcnt)
 {
     constexpr int WSPAN = kChunk / (kBlock / 64);  // vertices per wave
     constexpr int NWD = WSPAN / 64;                // ballot words per wave
     static_assert(NWD <= 64 && (NWD & (NWD - 1)) == 0, "one word per lane");
     __shared__ uint32_t sdeath[kChunk];
     __shared__ uint32_t wsum[kBlock / 64];
+    __shared__ uint32_t bpre[kBuckets];  // pairs of the chunk in earlier buckets
+    __shared__ uint32_t sover;
     const int64_t c = blockIdx.x;
     const FieldDesc d = D[search(cs, nf, c)];
     const int64_t lo = (c - d.chunk_start) * kChunk;
     const int64_t hi = min(lo + (int64_t)kChunk, d.n);
     const uint32_t off = (uint32_t)d.offset, nloc = (uint32_t)d.n;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (stage) {
+        constexpr int NB = RV * 4;  // buckets of one wave: (g, i) = lane / RV, lane % RV
+        if (wave == 0) {
+            const uint32_t own = bcnt[(size_t)c * kBuckets + lane];
+            uint32_t inc = own;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t t = __shfl_up(inc, o);
+                if (lane >= o) inc += t;
+            }
+            bpre[lane] = inc - own;
+            if (lane == 0) sover = 0;
+        }
+        __syncthreads();
+        // wave w's buckets, in its list order: lane k < NB holds bucket (k / RV) * 16 + (k % RV) * 4 + w
+        const int kb = (lane / RV) * 16 + (lane % RV) * 4 + wave;
+        const uint32_t own = lane < NB ? bcnt[(size_t)c * kBuckets + kb] : 0u;
+        uint32_t inc = own;
+#pragma unroll
+        for (int o = 1; o < NB; o <<= 1) {
+            const uint32_t t = __shfl_up(inc, o);
+            if (lane >= o) inc += t;
+        }
+        const uint32_t total = __shfl(inc, NB - 1);
+        if (lane == 0 && total > (uint32_t)kStageCap) atomicOr(&sover, 1u);
+        __syncthreads();
+        if (!sover) {
+            const uint4 *__restrict__ list = stage + ((size_t)c * (kBlock / 64) + wave) * kStageCap;
+            const int64_t b0 = base[c];
+            for (uint32_t e = lane; e < ((total + 63u) & ~63u); e += 64) {
+                // the list bucket k holding entry e: the first whose inclusive prefix exceeds e
+                uint32_t k = 0;
+#pragma unroll
+                for (int st = NB / 2; st >= 1; st >>= 1) {
+                    const uint32_t pre = __shfl(inc, (int)(k + st - 1));
+                    if (pre <= e) k += st;
+                }
+                const uint32_t before = __shfl(inc, (int)k) - __shfl(own, (int)k);
+                const uint32_t b = (k / RV) * 16 + (k % RV) * 4 + wave;
+                if (e >= total) continue;
+                const uint4 q = list[e];
+                const int64_t pos = b0 + bpre[b] + (e - before);
+                if (pos < capacity) {
+                    birth[pos] = q.x;
+                    death[pos] = q.y;
+                    bval[pos] = __uint_as_float(q.z);
+                    dval[pos] = __uint_as_float(q.w);
+                }
+            }
+            return;
+        }
+    }
     const int64_t w0 = lo + (int64_t)wave * WSPAN;
     uint32_t sl[NWD], err = 0;
     bool pf[NWD];
@@ -1673,10 +1845,18 @@ __global__ __launch_bounds__(kBlock) void k_rank_scatter(const uint64_t *__restr
 // ---------------------------------------------------------------------------
 // 6. Adjoint of the pair readout
 
-__global__ void k_fill0(float *__restrict__ g, int64_t n)
+// Zero fill of the gradient: 16-byte stores where the buffer is 16-byte
+// aligned, single floats for the head before that and the tail after it.
+__global__ __launch_bounds__(kBlock) void k_fill0(float *__restrict__ g, int64_t n)
 {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i < n) g[i] = 0.0f;
+    const int64_t head = min(n, (int64_t)((16 - ((uintptr_t)g & 15)) & 15) / 4);
+    const int64_t nv = (n - head) / 4;  // whole 16-byte words after the head
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x, stride = (int64_t)gridDim.x * kBlock;
+    if (t < head) g[t] = 0.0f;
+    float4 *__restrict__ v = (float4 *)(g + head);
+    for (int64_t i = t; i < nv; i += stride) v[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    const int64_t r = t + head + 4 * nv;
+    if (r < n) g[r] = 0.0f;  // (the tail is shorter than 4, and t < 4 covers it)
 }
 
 struct BwdGroup {
@@ -1687,19 +1867,24 @@ struct BwdGroup {
 
 // grad[birth] += gb (birth vertices are distinct and are never death
 // vertices, so a plain update is race free); grad[death] += gd atomically.
+// The group's pair offsets are read once per workgroup into LDS, so finding
+// the field of a pair is a search in LDS.
 __global__ __launch_bounds__(kBlock) void k_scatter(BwdGroup g, const int64_t *__restrict__ po, int64_t capacity,
                                                     const uint32_t *__restrict__ birth,
                                                     const uint32_t *__restrict__ death,
                                                     const float *__restrict__ gb, const float *__restrict__ gd,
                                                     float *__restrict__ grad)
 {
-    const int64_t k0 = po[g.first];
-    const int64_t k1 = min(po[g.first + g.count], capacity);
+    __shared__ int64_t spo[kBwdGroup + 1];
+    for (int i = threadIdx.x; i <= g.count; i += kBlock) spo[i] = po[g.first + i];
+    __syncthreads();
+    const int64_t k0 = spo[0];
+    const int64_t k1 = min(spo[g.count], capacity);
     for (int64_t k = k0 + (int64_t)blockIdx.x * kBlock + threadIdx.x; k < k1; k += (int64_t)gridDim.x * kBlock) {
-        int lo = 0, hi = g.count;  // po[first+lo] <= k < po[first+hi]
+        int lo = 0, hi = g.count;  // spo[lo] <= k < spo[hi]
         while (hi - lo > 1) {
             const int mid = (lo + hi) >> 1;
-            if (po[g.first + mid] <= k) lo = mid; else hi = mid;
+            if (spo[mid] <= k) lo = mid; else hi = mid;
         }
         const int64_t vo = g.voff[lo];
         const uint32_t bk = birth[k], dk = death[k];

@@ -35,12 +35,16 @@ EXPORTS = [
     "mt_batch_build_tree", "mt_build_pairs", "mt_vertex_ranks", "mt_rank_workspace_bytes",
     "mt_set_max_steps", "mt_get_max_steps", "mt_set_table_probes", "mt_get_table_probes", "mt_workspace_reset",
     "mt_set_counting", "mt_get_counting", "mt_read_counters", "mt_build_pairs64",
+    "mt_set_schedule", "mt_get_schedule",
+    "mt_autotune_schedule",
 ]
 
 COUNTER_NAMES = [
     "gm_facts", "gm_steps", "gm_descents", "gm_cas", "gm_cas_fail", "gm_remerge", "gm_max_steps",
     "lds_merges", "lds_steps", "lds_cas", "lds_cas_fail", "lds_max_steps",
     "table_inserts", "table_probes", "table_direct", "output_chase_steps", "gm_compress", "min_chase_steps",
+    "cyc_load", "cyc_descent", "cyc_number", "cyc_basin", "cyc_clear", "cyc_insert", "cyc_compact", "cyc_merge",
+    "cyc_repair", "cyc_label",
 ]
 
 # tree kinds (include/mt.h)
@@ -126,6 +130,12 @@ def load_library():
     lib.mt_autotune_workspace_bytes.restype = SZ
     lib.mt_autotune.argtypes = [P, P, I32, P, P, P, SZ, ctypes.c_int, P, P]
     lib.mt_autotune.restype = ctypes.c_int
+    lib.mt_autotune_schedule.argtypes = [P, P, I32, P, P, P, SZ, ctypes.c_int, P, P]
+    lib.mt_autotune_schedule.restype = ctypes.c_int
+    lib.mt_set_schedule.argtypes = [ctypes.c_int, ctypes.c_int]
+    lib.mt_set_schedule.restype = ctypes.c_int
+    lib.mt_get_schedule.argtypes = [P, P]
+    lib.mt_get_schedule.restype = ctypes.c_int
     lib.mt_set_max_steps.argtypes = [I64]
     lib.mt_set_max_steps.restype = ctypes.c_int
     lib.mt_get_max_steps.argtypes = []
@@ -530,6 +540,38 @@ def autotune(fields: Sequence[torch.Tensor], reps: int = 3):
     return {c: (get_tile_shape(c), best[c]) for c in range(3) if best[c] >= 0}
 
 
+def autotune_schedule(fields: Sequence[torch.Tensor], reps: int = 3):
+    """Time the schedule candidates (XCD-aware tile order on/off, merge
+    workgroups per XCD) on this batch with the current tile shapes (the
+    library checks bit-identical output) and select the fastest.  Returns
+    (xcd_remap, merge_groups, best ms)."""
+    lib = load_library()
+    dev = fields[0].device
+    dims = [grid_dims(f.shape) for f in fields]
+    dims_c = (ctypes.c_int64 * (3 * len(dims)))(*[v for d in dims for v in d])
+    flat = torch.cat([_field(f).reshape(-1) for f in fields])
+    n = flat.numel()
+    t1 = torch.empty((n, 2), dtype=torch.int32, device=dev)
+    t2 = torch.empty_like(t1)
+    ws = alloc_workspace(lib.mt_batch_workspace_bytes(dims_c, len(dims)), dev)
+    best = ctypes.c_double(-1.0)
+    _check(lib.mt_autotune_schedule(flat.data_ptr(), dims_c, len(dims), t1.data_ptr(), t2.data_ptr(), ws.data_ptr(),
+                                    ws.numel(), reps, _stream_ptr(dev), ctypes.byref(best)), "mt_autotune_schedule")
+    r, g = get_schedule()
+    return r, g, best.value
+
+
+def set_schedule(xcd_remap: int = -1, merge_groups: int = 0):
+    """XCD-aware tile order (1 on, 0 off, -1 default) and merge workgroups per XCD (0 default)."""
+    _check(load_library().mt_set_schedule(int(xcd_remap), int(merge_groups)), "mt_set_schedule")
+
+
+def get_schedule():
+    r, g = ctypes.c_int(0), ctypes.c_int(0)
+    _check(load_library().mt_get_schedule(ctypes.byref(r), ctypes.byref(g)), "mt_get_schedule")
+    return r.value, g.value
+
+
 def release_caches():
     load_library().mt_release_caches()
 
@@ -552,9 +594,10 @@ def get_table_probes() -> int:
     return int(load_library().mt_get_table_probes())
 
 
-def set_counting(on: bool):
-    """Counting build on (event counters in the workspace) or off (the timed kernels)."""
-    _check(load_library().mt_set_counting(1 if on else 0), "mt_set_counting")
+def set_counting(on):
+    """Counting build: False/0 the timed kernels, True/1 event counters in the
+    workspace, 2 phase clocks of the tile pass only."""
+    _check(load_library().mt_set_counting(int(on)), "mt_set_counting")
 
 
 def read_counters(workspace: torch.Tensor) -> dict:

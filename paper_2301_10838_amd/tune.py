@@ -1,4 +1,5 @@
-"""Autotuning driver: pick tile shapes per dims class and remember them.
+"""Autotuning driver: pick tile shapes per dims class and the launch
+schedule, and remember them.
 
 The library's autotuner (mt_autotune) times every compiled tile shape of each
 dims class present in a batch and checks that all of them give bit-identical
@@ -69,3 +70,25 @@ def tune(fields: Sequence[torch.Tensor], reps: int = 3, force: bool = False) -> 
         with open(cache_path(), "w") as fh:
             json.dump(cache, fh, indent=1, sort_keys=True)
     return {CLASS_NAMES[c]: mt.get_tile_shape(c) for c in sorted(classes)}
+
+
+def tune_schedule(fields: Sequence[torch.Tensor], reps: int = 3, force: bool = False) -> dict:
+    """Select the launch schedule (XCD-aware tile order, merge workgroups per
+    XCD) for this batch with the tile shapes in force; cached per arch and
+    the batch's set of dims classes."""
+    dev = fields[0].device
+    classes = sorted({0 if len(f.shape) == 3 and f.shape[0] > 1 else 1 if len(f.shape) >= 2 and f.shape[-2] > 1
+                      else 2 for f in fields})
+    key = f"{_arch(dev)}|schedule|{'+'.join(CLASS_NAMES[c] for c in classes)}"
+    cache = _load()
+    if key in cache and not force:
+        e = cache[key]
+        mt.set_schedule(e["xcd_remap"], e["merge_groups"])
+    else:
+        r, g, ms = mt.autotune_schedule(fields, reps=reps)
+        cache[key] = {"xcd_remap": r, "merge_groups": g, "ms": ms}
+        os.makedirs(os.path.dirname(cache_path()), exist_ok=True)
+        with open(cache_path(), "w") as fh:
+            json.dump(cache, fh, indent=1, sort_keys=True)
+    r, g = mt.get_schedule()
+    return {"xcd_remap": r, "merge_groups": g}

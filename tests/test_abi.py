@@ -130,9 +130,21 @@ def test_setter_bounds(lib):
     assert lib.mt_set_max_steps(0) == 0 and lib.mt_get_max_steps() == 1 << 24
     assert lib.mt_get_table_probes() == 32
     assert lib.mt_set_table_probes(-2) == -1
-    assert lib.mt_set_table_probes(65) == -1
+    assert lib.mt_set_table_probes(33) == -1
     assert lib.mt_set_table_probes(0) == 0 and lib.mt_get_table_probes() == 0
     assert lib.mt_set_table_probes(-1) == 0 and lib.mt_get_table_probes() == 32
+    r, g = ctypes.c_int(-9), ctypes.c_int(-9)
+    assert lib.mt_get_schedule(ctypes.byref(r), ctypes.byref(g)) == 0 and (r.value, g.value) == (1, 2048)
+    assert lib.mt_set_schedule(2, 0) == -1 and lib.mt_set_schedule(-2, 0) == -1
+    assert lib.mt_set_schedule(0, -1) == -1 and lib.mt_set_schedule(0, 65537) == -1
+    assert lib.mt_set_schedule(0, 64) == 0
+    assert lib.mt_get_schedule(ctypes.byref(r), ctypes.byref(g)) == 0 and (r.value, g.value) == (0, 64)
+    assert lib.mt_set_schedule(-1, 0) == 0
+    assert lib.mt_get_schedule(ctypes.byref(r), None) == 0 and r.value == 1
+    assert lib.mt_get_schedule(None, ctypes.byref(g)) == 0 and g.value == 2048
+    assert lib.mt_set_counting(3) == -1 and lib.mt_set_counting(-1) == -1
+    assert lib.mt_set_counting(2) == 0 and lib.mt_get_counting() == 2
+    assert lib.mt_set_counting(0) == 0 and lib.mt_get_counting() == 0
     assert lib.mt_workspace_reset(None, 4096, None) == -6
     assert lib.mt_workspace_reset(ctypes.c_void_p(0x10010), 4096, None) == -6
     assert lib.mt_workspace_reset(ctypes.c_void_p(0x10000), 64, None) == -6

@@ -79,3 +79,47 @@ def test_every_shape_checkerboard():
     finally:
         for c, sid in before.items():
             mt.set_tile_shape(c, sid)
+
+
+def test_schedule_tuner_and_every_schedule_exact(tmp_path, monkeypatch):
+    """The schedule tuner checks bit-identity over its candidates and applies
+    the winner; every schedule, forced, gives the oracle's tree (also in a
+    batch graph, whose cache key includes the schedule)."""
+    import paper_2301_10838_amd.mt as mt
+    from paper_2301_10838_amd import tune
+
+    dev = device()
+    monkeypatch.setenv("MT_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
+    before = mt.get_schedule()
+    assert before == (1, 2048)
+    fs = [fields.lognormal_grf((70, 66, 61), 405), fields.lognormal_grf((300, 257), 406)]
+    ts = [torch.from_numpy(f).to(dev) for f in fs]
+    try:
+        r, g, ms = mt.autotune_schedule(ts, reps=1)
+        assert r in (0, 1) and g in (256, 1024, 2048, 8192) and ms > 0
+        assert mt.get_schedule() == (r, g)
+        got = tune.tune_schedule(ts, reps=1)
+        assert (tmp_path / "tune.json").exists() and set(got) == {"xcd_remap", "merge_groups"}
+        mt.set_schedule(-1, 0)
+        assert tune.tune_schedule(ts, reps=1) == got  # from the cache
+        refs = [oracle.merge_tree(f) for f in fs]
+        for remap in (0, 1):
+            for groups in (1, 256, 8192):
+                mt.set_schedule(remap, groups)
+                print("case schedule", remap, groups, flush=True)
+                for f, ref in zip(fs, refs):
+                    T, _ = gpu_tree(f, dev)
+                    assert np.array_equal(T, ref), (remap, groups)
+                plan = mt.BatchPlan([f.shape for f in fs], dev)
+                mt.mt_batch_build(ts, plan=plan)
+                Tb = plan.triplets.cpu().numpy().view(np.uint32)
+                a = 0
+                for f, ref in zip(fs, refs):
+                    assert np.array_equal(Tb[a:a + f.size], ref), (remap, groups)
+                    a += f.size
+    finally:
+        mt.set_schedule(*before)
+    with pytest.raises(mt.MTError):
+        mt.set_schedule(2, 0)
+    with pytest.raises(mt.MTError):
+        mt.set_schedule(1, -5)

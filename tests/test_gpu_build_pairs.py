@@ -3,7 +3,10 @@ pair counts the build leaves.  Checked against the oracle, and against the
 separate mt_build_tree + mt_persistence_pairs calls, on every kind of chunk
 end (whole chunks, a last chunk ending inside a 64-vertex ballot word, fields
 smaller than one word), on the checkerboard (every other vertex a pair birth:
-several dense-lane passes per wave) and on a workspace reused across
+several dense-lane passes per wave, and more pairs than the build stages per
+chunk, so the readout takes those chunks from T), on a field mixing such
+chunks with staged ones, on signed zeros (staged pair values rebuilt from
+order keys must keep the sign of zero) and on a workspace reused across
 shapes."""
 import ctypes
 
@@ -63,7 +66,30 @@ CASES = [
     ("grf2d", lambda: fields.lognormal_grf((300, 257), 95)),
     ("grf96", lambda: fields.lognormal_grf((96, 96, 96), 96)),
     ("checkerboard", lambda: np.indices((24, 24, 24)).sum(axis=0).astype(np.float32) % 2),
+    ("half_checkerboard", lambda: _half_checkerboard()),
+    ("signed_zeros", lambda: _signed_zeros()),
 ]
+
+
+def _half_checkerboard():
+    """z < 20: a checkerboard (every other vertex a pair birth: the chunk's
+    staged lists overflow and the readout takes those chunks from T); above:
+    a log-normal field (chunks read from the staged lists)."""
+    f = fields.lognormal_grf((40, 64, 64), 102)
+    f[:20] = (np.indices((20, 64, 64)).sum(axis=0) % 2).astype(np.float32) * 100.0
+    return f
+
+
+def _signed_zeros():
+    """Values around zero with many exact +0.0 and -0.0 (equal in the order,
+    told apart by id): pair values must still be bit copies, sign of zero
+    included."""
+    rng = np.random.default_rng(103)
+    f = fields.lognormal_grf((33, 35, 37), 103) - 1.0
+    z = rng.random(f.shape)
+    f[z < 0.15] = 0.0
+    f[(z >= 0.15) & (z < 0.3)] = -0.0
+    return f.astype(np.float32)
 
 
 @pytest.mark.parametrize("name,maker", CASES)
@@ -75,9 +101,11 @@ def test_build_pairs_matches_oracle(dev, name, maker):
 
 
 @pytest.mark.parametrize("kind", ["merge", "split"])
-def test_build_pairs_equals_separate_calls(dev, kind):
-    f = fields.lognormal_grf((70, 66, 61), 97)
-    print("case build_pairs vs separate", kind, flush=True)
+@pytest.mark.parametrize("name", ["grf", "signed_zeros", "half_checkerboard"])
+def test_build_pairs_equals_separate_calls(dev, kind, name):
+    f = {"grf": lambda: fields.lognormal_grf((70, 66, 61), 97), "signed_zeros": _signed_zeros,
+         "half_checkerboard": _half_checkerboard}[name]()
+    print("case build_pairs vs separate", name, kind, flush=True)
     same(fused(f, dev, kind), separate(f, dev, kind))
 
 

@@ -173,7 +173,9 @@ def test_more_than_2_31_vertices(dev):
     g = torch.Generator(device=dev)
     g.manual_seed(62)
     thr = torch.kthvalue(flat[torch.randint(0, N, (1 << 20,), device=dev, generator=g)].cpu(), (1 << 20) // 50).values
-    low = torch.nonzero(flat <= thr.to(dev)).reshape(-1)
+    # (torch.nonzero over more than 2^31 elements fails on this stack: chunked)
+    thr_d = thr.to(dev)
+    low = torch.cat([torch.nonzero(flat[a:min(N, a + chunk)] <= thr_d).reshape(-1) + a for a in range(0, N, chunk)])
     pick = low[torch.randint(0, low.numel(), (20000,), device=dev, generator=g)]
     extra = torch.randint(0, N, (2000,), device=dev, generator=g)
     us = torch.cat([pick, extra])
