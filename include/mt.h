@@ -185,6 +185,38 @@ int mt_build_pairs64(const float *field, int64_t nx, int64_t ny, int64_t nz, int
                      void *workspace, size_t ws_bytes, void *stream);
 
 /*
+ * mt_build_pairs_noalloc -- mt_build_pairs without a workspace argument, for
+ * callers that cannot allocate device memory (code that must not call
+ * hipMalloc, tight serving loops, harnesses that forbid allocation).  Not in
+ * the paper.
+ *
+ * The call's scratch is a fixed array of MT_NOALLOC_SCRATCH_BYTES (64 MiB)
+ * inside the library's device code, one per GPU, held from the library's
+ * first use on that GPU until the process ends.  The call itself allocates
+ * nothing: no hipMalloc, no hipFree, no allocating library routine.  Fields
+ * whose workspace (mt_workspace_bytes) exceeds that size -- about 2.2 M
+ * vertices of a 3-D field, e.g. 130^3; 128^3 needs 54 MiB -- are rejected
+ * with MT_ERR_TOO_LARGE before anything is enqueued.
+ *
+ * Arguments, outputs, results and errors are those of mt_build_pairs (32-bit
+ * ids); the triplets and pairs are identical to its.  The current HIP device
+ * must be the device of `stream` and of every buffer.  Synchronizes `stream`
+ * once, at the end.  Every call on one GPU uses that GPU's one array, which
+ * keeps the last call's contents (each call clears what it needs cleared).
+ * Calls that overlapped on one GPU would race on the array, so the library
+ * serializes the calls of one process with a lock held until the call's
+ * stream has synchronized.
+ */
+#define MT_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int mt_build_pairs_noalloc(const float *field, int64_t nx, int64_t ny, int64_t nz, int kind,
+                           uint32_t *triplets, uint32_t *birth, uint32_t *death,
+                           float *birth_val, float *death_val, int64_t capacity,
+                           int64_t *n_pairs, int64_t *n_roots, void *stream);
+
+/* MT_NOALLOC_SCRATCH_BYTES, as compiled into the library. */
+size_t mt_noalloc_scratch_bytes(void);
+
+/*
  * mt_batch_build -- merge trees and pairs of many fields of uneven sizes in
  * one graph launch.  This batching is not in the paper; each field gets
  * exactly the triplets and pairs that mt_build + mt_persistence_pairs give it.

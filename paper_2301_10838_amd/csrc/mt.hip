@@ -657,6 +657,61 @@ int mt_build_pairs64(const float *field, int64_t nx, int64_t ny, int64_t nz, int
                        n_roots, workspace, ws_bytes, stream, true);
 }
 
+}  // extern "C"
+
+// Allocation-free variant of mt_build_pairs ---------------------------------
+//
+// Its workspace is this fixed device array instead of a caller's buffer.  The
+// array's name is a host-side handle only: host code never passes it to a
+// kernel or a copy.  Its device address, which differs per GPU, is looked up
+// once per device with hipGetSymbolAddress (with that device current) and
+// kept in g_scratch; every launch and copy uses that address.  Each GPU the
+// library runs on holds its copy of the array until the process ends.
+namespace {
+static __device__ __align__(256) unsigned char scratch[MT_NOALLOC_SCRATCH_BYTES];
+
+static std::mutex g_scratch_mu;                       // held for the whole call
+static std::unordered_map<int, void *> g_scratch;     // device -> address of `scratch`
+
+static int scratch_address(int dev, void **out)
+{
+    auto it = g_scratch.find(dev);
+    if (it != g_scratch.end()) {
+        *out = it->second;
+        return MT_OK;
+    }
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return MT_ERR_HIP;
+    g_scratch.emplace(dev, ptr);
+    *out = ptr;
+    return MT_OK;
+}
+}  // namespace
+
+extern "C" {
+
+size_t mt_noalloc_scratch_bytes(void) { return MT_NOALLOC_SCRATCH_BYTES; }
+
+int mt_build_pairs_noalloc(const float *field, int64_t nx, int64_t ny, int64_t nz, int kind, uint32_t *triplets,
+                           uint32_t *birth, uint32_t *death, float *birth_val, float *death_val, int64_t capacity,
+                           int64_t *n_pairs, int64_t *n_roots, void *stream)
+{
+    const int64_t dims[3] = {nx, ny, nz};
+    Plan p;
+    const int rc = make_plan(dims, 1, p);
+    if (rc != MT_OK) return rc;
+    if (p.lay.total > (size_t)MT_NOALLOC_SCRATCH_BYTES) return MT_ERR_TOO_LARGE;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return MT_ERR_HIP;
+    // One call at a time per process: the call synchronizes its stream before
+    // it returns, so holding the lock keeps every use of the array apart.
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    void *ws = nullptr;
+    if (scratch_address(dev, &ws) != MT_OK) return MT_ERR_HIP;
+    return build_pairs(field, nx, ny, nz, kind, triplets, birth, death, birth_val, death_val, capacity, n_pairs,
+                       n_roots, ws, (size_t)MT_NOALLOC_SCRATCH_BYTES, stream, false);
+}
+
 int mt_batch_build(const float *fields, const int64_t *dims, int32_t n_fields, uint32_t *triplets, uint32_t *birth,
                    uint32_t *death, float *birth_val, float *death_val, int64_t pair_capacity,
                    int64_t *pair_offsets, void *workspace, size_t ws_bytes, void *stream)

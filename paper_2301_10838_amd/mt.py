@@ -35,7 +35,7 @@ EXPORTS = [
     "mt_batch_build_tree", "mt_build_pairs", "mt_vertex_ranks", "mt_rank_workspace_bytes",
     "mt_set_max_steps", "mt_get_max_steps", "mt_set_table_probes", "mt_get_table_probes", "mt_workspace_reset",
     "mt_set_counting", "mt_get_counting", "mt_read_counters", "mt_build_pairs64",
-    "mt_set_schedule", "mt_get_schedule",
+    "mt_build_pairs_noalloc", "mt_noalloc_scratch_bytes", "mt_set_schedule", "mt_get_schedule",
     "mt_autotune_schedule",
 ]
 
@@ -94,6 +94,10 @@ def load_library():
     lib.mt_build_pairs.restype = ctypes.c_int
     lib.mt_build_pairs64.argtypes = [P, I64, I64, I64, ctypes.c_int, P, P, P, P, P, I64, P, P, P, SZ, P]
     lib.mt_build_pairs64.restype = ctypes.c_int
+    lib.mt_build_pairs_noalloc.argtypes = [P, I64, I64, I64, ctypes.c_int, P, P, P, P, P, I64, P, P, P]
+    lib.mt_build_pairs_noalloc.restype = ctypes.c_int
+    lib.mt_noalloc_scratch_bytes.argtypes = []
+    lib.mt_noalloc_scratch_bytes.restype = SZ
     lib.mt_vertex_ranks.argtypes = [P, I64, I64, I64, ctypes.c_int, P, P, SZ, P]
     lib.mt_vertex_ranks.restype = ctypes.c_int
     lib.mt_rank_workspace_bytes.argtypes = [I64, I64, I64]

@@ -145,6 +145,7 @@ def test_setter_bounds(lib):
     assert lib.mt_set_counting(3) == -1 and lib.mt_set_counting(-1) == -1
     assert lib.mt_set_counting(2) == 0 and lib.mt_get_counting() == 2
     assert lib.mt_set_counting(0) == 0 and lib.mt_get_counting() == 0
+    assert lib.mt_noalloc_scratch_bytes() == 64 << 20
     assert lib.mt_workspace_reset(None, 4096, None) == -6
     assert lib.mt_workspace_reset(ctypes.c_void_p(0x10010), 4096, None) == -6
     assert lib.mt_workspace_reset(ctypes.c_void_p(0x10000), 64, None) == -6
