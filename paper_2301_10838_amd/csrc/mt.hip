@@ -351,11 +351,11 @@ static int enqueue_setup(const Plan &p, const Ptrs &w, uint32_t clear_status, bo
     return MT_OK;
 }
 
-template <class S, int MODE>
+template <class S, int MODE, bool LIMIT>
 static int launch_local_as(const Plan &p, const ClassLaunch &cl, const Ptrs &w, const float *f, uint32_t flip,
                            hipStream_t st)
 {
-    auto *const kern = &k_local<S, MODE>;
+    auto *const kern = &k_local<S, MODE, LIMIT>;
     MT_LAUNCH("k_local", kern, dim3((unsigned)cl.ntiles), dim3(S::NT), st, f, w.lbl,
               w.slot, w.mkey, (const FieldDesc *)w.D, (const int32_t *)w.tfield + cl.cb,
               (const int64_t *)w.tstart + cl.cb, cl.nfc, cl.tile0, cl.ntiles, p.remap, (uint32_t)p.m_cap, p.cap,
@@ -367,8 +367,12 @@ template <class S>
 static int launch_local(const Plan &p, const ClassLaunch &cl, const Ptrs &w, const float *f, uint32_t flip,
                         hipStream_t st)
 {
-    if (p.count == 2) return launch_local_as<S, 2>(p, cl, w, f, flip, st);
-    return p.count ? launch_local_as<S, 1>(p, cl, w, f, flip, st) : launch_local_as<S, 0>(p, cl, w, f, flip, st);
+    // a table-probe bound below the maximum only matters to tests of the
+    // fallback paths: its instantiation (timed kernel only) checks the bound
+    if (p.probes < (uint32_t)kMaxProbes) return launch_local_as<S, 0, true>(p, cl, w, f, flip, st);
+    if (p.count == 2) return launch_local_as<S, 2, false>(p, cl, w, f, flip, st);
+    return p.count ? launch_local_as<S, 1, false>(p, cl, w, f, flip, st)
+                   : launch_local_as<S, 0, false>(p, cl, w, f, flip, st);
 }
 
 template <class S>

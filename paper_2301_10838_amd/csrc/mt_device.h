@@ -324,6 +324,18 @@ __device__ __forceinline__ uint64_t lanemask_lt()
     return lane ? (~0ull >> (64 - lane)) : 0ull;
 }
 
+// Position of the k-th set bit (k < popcount) of a 64-bit word, by halving.
+__device__ __forceinline__ uint32_t select_bit(uint64_t m, uint32_t k)
+{
+    uint32_t pos = 0;
+#pragma unroll
+    for (int w = 32; w >= 1; w >>= 1) {
+        const uint32_t c = (uint32_t)__popcll(m & ((1ull << w) - 1));
+        if (k >= c) { k -= c; pos += w; m >>= w; }
+    }
+    return pos;
+}
+
 // Tile shape and workgroup size.
 template <int X, int Y, int Z, int NTHREADS>
 struct Shape {
@@ -442,13 +454,18 @@ __device__ void lds_merge(uint64_t *TL, const uint32_t *hk, const uint16_t *mh, 
     tc.add(C_LDS_MERGES);
     if (u >= cnt || v >= cnt) { err |= ST_CORRUPT; return; }
     uint64_t tu = lds_ld64(TL + u), tv = lds_ld64(TL + v);
-    uint32_t step = 0;
-    for (; step < cap; ++step) {
+    // (every exit returns from inside the loop: the timed build, in which
+    // done() is empty, keeps the loop's exits apart)
+    auto done = [&](uint32_t steps) {
+        tc.add(C_LDS_STEPS, steps);
+        tc.max(C_LDS_MAX_STEPS, steps);
+    };
+    for (uint32_t step = 0; step < cap; ++step) {
         const uint32_t u1 = L::tgt(tu), v1 = L::tgt(tv);
-        if (u1 >= cnt || v1 >= cnt) { err |= ST_CORRUPT; break; }
+        if (u1 >= cnt || v1 >= cnt) { err |= ST_CORRUPT; done(step + 1); return; }
         if (u1 != u && L::key(tu) < ks) { u = u1; tu = lds_ld64(TL + u); continue; }
         if (v1 != v && L::key(tv) < ks) { v = v1; tv = lds_ld64(TL + v); continue; }
-        if (u == v) break;
+        if (u == v) { done(step + 1); return; }
         if (lkey<L::PB>(hk, mh[v]) < lkey<L::PB>(hk, mh[u])) {
             const uint32_t w = u; u = v; v = w;
             const uint64_t tw = tu; tu = tv; tv = tw;
@@ -457,7 +474,7 @@ __device__ void lds_merge(uint64_t *TL, const uint32_t *hk, const uint16_t *mh, 
         tc.add(C_LDS_CAS);
         if (__hip_atomic_compare_exchange_strong(TL + v, &seen, L::make(ks, u), __ATOMIC_RELAXED,
                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) {
-            if (L::tgt(tv) == v) break;
+            if (L::tgt(tv) == v) { done(step + 1); return; }
             ks = L::key(tv);
             v = L::tgt(tv);
             tv = lds_ld64(TL + v);
@@ -467,16 +484,15 @@ __device__ void lds_merge(uint64_t *TL, const uint32_t *hk, const uint16_t *mh, 
         }
         tu = lds_ld64(TL + u);
     }
-    tc.add(C_LDS_STEPS, step + (step < cap));
-    tc.max(C_LDS_MAX_STEPS, step + (step < cap));
-    if (step == cap) err |= ST_LIVELOCK;
+    done(cap);
+    err |= ST_LIVELOCK;
 }
 
 // MODE 0: the timed kernel; 1: counting build (event counts); 2: phase
 // clocks only (the tile pass's phases timed by the workgroup's first lane
 // into LDS, added to the counters once per workgroup; no event counts, whose
 // per-lane registers would slow the phases down).
-template <class S, int MODE>
+template <class S, int MODE, bool LIMIT>
 __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f, uint32_t *__restrict__ lbl,
                                                  Slot *__restrict__ slot, uint64_t *__restrict__ mkey,
                                                  const FieldDesc *__restrict__ D, const int32_t *__restrict__ tfield,
@@ -709,14 +725,17 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
     // only costs a merge that changes nothing.  `probes` (at most 32 by
     // default) bounds the probes before the direct merge; a smaller value only
     // sends more edges down that path.
+    // (The probe loops have a compile-time length and are unrolled: measurably
+    // faster than a loop to a runtime bound.  With the default bound, the
+    // maximum, the kernel is instantiated without any bound check (LIMIT
+    // false); a smaller bound selects the instantiation that checks it.)
     auto insert = [&](uint64_t val) {
         tc.add(C_TAB_INSERTS);
         uint32_t si = ((uint32_t)(val & TAGM) * 0x9E3779B1u) >> (32 - PB);
-        // (a loop of compile-time length, unrolled: measurably faster than a
-        // loop to the runtime bound)
-#pragma unroll
         for (int probe = 0; probe < kMaxProbes; ++probe) {
-            if ((uint32_t)probe >= probes) break;
+            if constexpr (LIMIT) {
+                if ((uint32_t)probe >= probes) break;
+            }
             tc.add(C_TAB_PROBES);
             const uint64_t prev = __hip_atomic_fetch_min(htab + si, val, __ATOMIC_RELAXED,
                                                          __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -1656,18 +1675,6 @@ __global__ __launch_bounds__(1024) void k_pairs_scan(uint32_t *__restrict__ cnt,
         h->total_pairs = (int64_t)total;
         if ((int64_t)total > capacity) atomicOr(&h->status, ST_CAPACITY);
     }
-}
-
-// Position of the k-th set bit (k < popcount) of a 64-bit word, by halving.
-__device__ __forceinline__ uint32_t select_bit(uint64_t m, uint32_t k)
-{
-    uint32_t pos = 0;
-#pragma unroll
-    for (int w = 32; w >= 1; w >>= 1) {
-        const uint32_t c = (uint32_t)__popcll(m & ((1ull << w) - 1));
-        if (k >= c) { k -= c; pos += w; m >>= w; }
-    }
-    return pos;
 }
 
 // Ordered compaction: ascending vertex id within the chunk, chunks in order.
