@@ -468,13 +468,22 @@ class MergeTreePairs(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, g_birth, g_death):
+        # (one C call with the plan's prepared arguments: this runs once per
+        # optimisation step, so its host time is part of the step)
         plan, P = ctx.plan, ctx.P
         dev = plan.device
-        gb = torch.zeros(P, dtype=torch.float32, device=dev) if g_birth is None else g_birth.float()
-        gd = torch.zeros(P, dtype=torch.float32, device=dev) if g_death is None else g_death.float()
+        if g_birth is None:
+            g_birth = torch.zeros(P, dtype=torch.float32, device=dev)
+        if g_death is None:
+            g_death = torch.zeros(P, dtype=torch.float32, device=dev)
+        gb = g_birth.contiguous().float()
+        gd = g_death.contiguous().float()
         birth, death, offsets = ctx.saved_tensors
         grad = torch.empty(plan.n_total, dtype=torch.float32, device=dev)
-        mt_pairs_backward(plan._dims_c, len(plan.dims), offsets, P, birth, death, gb, gd, grad)
+        _check(load_library().mt_pairs_backward(plan._dims_c, len(plan.dims), offsets.data_ptr(), P,
+                                                birth.data_ptr(), death.data_ptr(), gb.data_ptr(), gd.data_ptr(),
+                                                grad.data_ptr(), 0, torch.cuda.current_stream(dev).cuda_stream),
+               "mt_pairs_backward")
         return grad, None
 
 
