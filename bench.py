@@ -623,6 +623,61 @@ def progress(msg: str):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
+def summarize_counters(dirs, workload: str, command: str):
+    """Turn rocprofv3 SQ counter passes (CSV) into profiles/counters_<workload>.md:
+    per kernel, the instruction mix per wave and the share of the waves'
+    resident cycles spent issuing and waiting (SQ_*_CYCLES and SQ_WAIT_* count
+    in units of four cycles, alike, so their ratios need no scale)."""
+    import csv
+    import glob
+
+    per = {}
+    for d in dirs:
+        path = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+        if not path:
+            raise FileNotFoundError(f"no counter_collection.csv under {d}")
+        with open(path[0]) as fh:
+            for r in csv.DictReader(fh):
+                per.setdefault(r["Kernel_Name"], {}).setdefault(r["Counter_Name"], []).append(
+                    float(r["Counter_Value"]))
+    avg = {k: {c: sum(v) / len(v) for c, v in cs.items()} for k, cs in per.items()}
+    order = ["k_local", "k_repair_reg", "k_merge_q", "k_cross", "k_repair_min", "k_pairs_write", "k_qscatter"]
+    lines = [f"# rocprofv3 SQ counters: {workload}", "", "Command (run from /tmp with TMPDIR=/tmp), one run per pass:",
+             "", "```", command, "```", "",
+             "Per launch (average over launches). Instructions are counted per wave; cycle counters are in the "
+             "SQ's four-cycle units, so only their ratios are used.", "",
+             "| Kernel | waves | VALU/wave | SALU/wave | LDS/wave | VMEM rd/wave | VMEM wr/wave | issuing | "
+             "waiting | LDS bank-conflict share of LDS cycles |",
+             "|---|---|---|---|---|---|---|---|---|---|"]
+
+    def g(k, c):
+        return avg[k].get(c)
+
+    for k in order:
+        if k not in avg:
+            continue
+        w = g(k, "SQ_WAVES") or 0
+        def pw(c):
+            v = g(k, c)
+            return f"{v / w:.0f}" if (v is not None and w) else "-"
+        wc = g(k, "SQ_WAVE_CYCLES")
+        iss = f"{g(k, 'SQ_ACTIVE_INST_ANY') / wc:.2f}" if wc and g(k, "SQ_ACTIVE_INST_ANY") is not None else "-"
+        wt = f"{g(k, 'SQ_WAIT_ANY') / wc:.2f}" if wc and g(k, "SQ_WAIT_ANY") is not None else "-"
+        lds = g(k, "SQ_ACTIVE_INST_LDS")
+        bc = f"{g(k, 'SQ_LDS_BANK_CONFLICT') / lds:.2f}" if lds else "-"
+        lines.append(f"| {k} | {w:.0f} | {pw('SQ_INSTS_VALU')} | {pw('SQ_INSTS_SALU')} | {pw('SQ_INSTS_LDS')} | "
+                     f"{pw('SQ_INSTS_VMEM_RD')} | {pw('SQ_INSTS_VMEM_WR')} | {iss} | {wt} | {bc} |")
+    lines += ["", "Raw averages per launch:", ""]
+    for k in order:
+        if k in avg:
+            lines.append(f"- `{k}`: " + ", ".join(f"{c} {v:.4g}" for c, v in sorted(avg[k].items())))
+    lines.append("")
+    out = os.path.join(ROOT, "profiles", f"counters_{workload}.md")
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines))
+    print(out)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -635,10 +690,15 @@ def main():
                     help="also run a plain 1 GiB device copy (3 times), the reference for HBM counters")
     ap.add_argument("--summarize-profiles", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/ summaries from rocprofv3 CSV output and exit (no GPU)")
+    ap.add_argument("--summarize-counters", nargs="+", metavar="PASS_DIR",
+                    help="write profiles/counters_<workload>.md from rocprofv3 SQ counter passes and exit (no GPU)")
     ap.add_argument("--profile-command", default="", help="command line recorded in the summary")
     args = ap.parse_args()
     if args.summarize_profiles:
         summarize_profiles(*args.summarize_profiles, args.workload, args.profile_command)
+        return
+    if args.summarize_counters:
+        summarize_counters(args.summarize_counters, args.workload, args.profile_command)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
