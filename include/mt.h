@@ -303,6 +303,9 @@ int mt_build_stats(const void *workspace, void *stream, int64_t *n_local_minima,
  * grad_field with the result, 1 adds to it.  Birth vertices never repeat;
  * death vertices can (several branches may die at one saddle) and are summed
  * with float atomics, so the rounding order of such sums is not fixed.
+ * Pairs whose two upstream gradients are zero are skipped, and so is either
+ * update of zero (adding a zero changes no value, only possibly the sign of
+ * a zero already there).
  * pair_capacity bounds the number of pairs read.  Asynchronous.
  */
 int mt_pairs_backward(const int64_t *dims, int32_t n_fields, const int64_t *pair_offsets,

@@ -454,6 +454,10 @@ __device__ void lds_merge(uint64_t *TL, const uint32_t *hk, const uint16_t *mh, 
     tc.add(C_LDS_MERGES);
     if (u >= cnt || v >= cnt) { err |= ST_CORRUPT; return; }
     uint64_t tu = lds_ld64(TL + u), tv = lds_ld64(TL + v);
+    // A word's key lies below ks exactly when the word lies below ks << TB
+    // (its target fills the low TB bits), so the descent tests compare whole
+    // words; a replacement word (ks, u) is that bound with u in the low bits.
+    uint64_t ksT = ks << L::TB;
     // (every exit returns from inside the loop: the timed build, in which
     // done() is empty, keeps the loop's exits apart)
     auto done = [&](uint32_t steps) {
@@ -463,19 +467,29 @@ __device__ void lds_merge(uint64_t *TL, const uint32_t *hk, const uint16_t *mh, 
     for (uint32_t step = 0; step < cap; ++step) {
         const uint32_t u1 = L::tgt(tu), v1 = L::tgt(tv);
         if (u1 >= cnt || v1 >= cnt) { err |= ST_CORRUPT; done(step + 1); return; }
-        if (u1 != u && L::key(tu) < ks) { u = u1; tu = lds_ld64(TL + u); continue; }
-        if (v1 != v && L::key(tv) < ks) { v = v1; tv = lds_ld64(TL + v); continue; }
+        // one descent step, u's before v's: a link below the merge's level
+        const bool du = u1 != u && tu < ksT;
+        const bool dv = v1 != v && tv < ksT;
+        if (du || dv) {
+            const uint32_t x = du ? u1 : v1;
+            const uint64_t t = lds_ld64(TL + x);
+            if (du) { u = x; tu = t; } else { v = x; tv = t; }
+            continue;
+        }
         if (u == v) { done(step + 1); return; }
-        if (lkey<L::PB>(hk, mh[v]) < lkey<L::PB>(hk, mh[u])) {
+        // the upper minimum is re-pointed: tile keys compared as (value key, position)
+        const uint32_t pu = mh[u], pv = mh[v];
+        const uint32_t ku = hk[pu], kv = hk[pv];
+        if (kv < ku || (kv == ku && pv < pu)) {
             const uint32_t w = u; u = v; v = w;
             const uint64_t tw = tu; tu = tv; tv = tw;
         }
         uint64_t seen = tv;
         tc.add(C_LDS_CAS);
-        if (__hip_atomic_compare_exchange_strong(TL + v, &seen, L::make(ks, u), __ATOMIC_RELAXED,
+        if (__hip_atomic_compare_exchange_strong(TL + v, &seen, ksT | u, __ATOMIC_RELAXED,
                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) {
             if (L::tgt(tv) == v) { done(step + 1); return; }
-            ks = L::key(tv);
+            ksT = tv & ~L::TM;  // merge the displaced triplet again, at its own level
             v = L::tgt(tv);
             tv = lds_ld64(TL + v);
         } else {
@@ -585,12 +599,17 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
     __syncthreads();
     phase(C_PH_LOAD);
 
-    // lowest lower neighbour inside the tile
+    // lowest lower neighbour inside the tile; a position outside the field
+    // points at itself, so that the basin pass can follow every pointer
+    // without a test
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
         const int p = k * NT + threadIdx.x;
         const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
-        if (!valid(lx, ly, lz)) continue;
+        if (!valid(lx, ly, lz)) {
+            wl[p] = (int16_t)p;
+            continue;
+        }
         uint64_t best = lkey<PB>(hk, p);
         int bp = p;
 #define MT_CAND(cond, q)                                                                    \
@@ -666,31 +685,28 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
 
     // local basins: follow the pointers to the local minimum (keys fall
     // strictly along them, so at most VOL steps); a lane follows the chains
-    // of all its vertices together so that their loads overlap
+    // of all its vertices together so that their loads overlap, and every
+    // read is issued with no test around it: a finished chain sits on its
+    // minimum, and a position outside the field on itself, both pointing at
+    // themselves
     {
         int xs[PER];
-        uint32_t act = 0;
+        uint32_t moved = 0;
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
             const int p = k * NT + threadIdx.x;
-            const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
-            xs[k] = p;
-            if (valid(lx, ly, lz) && wl[p] != p) act |= 1u << k;
+            xs[k] = wl[p];
+            moved |= (uint32_t)(xs[k] != p) << k;
         }
-        const uint32_t moved = act;
-        // every read is issued, with no branch around it: a finished chain
-        // sits on its minimum, which points at itself, and a position outside
-        // the field reads an entry of the tile that is then discarded
-        for (int step = 0; act != 0 && step < VOL; ++step) {
+        bool more = moved != 0;
+        for (int step = 0; more && step < VOL; ++step) {
             int ys[PER];
 #pragma unroll
-            for (int k = 0; k < PER; ++k) {
-                const int y = wl[xs[k]];
-                ys[k] = (act >> k) & 1u ? y : xs[k];
-            }
+            for (int k = 0; k < PER; ++k) ys[k] = wl[xs[k]];
+            more = false;
 #pragma unroll
             for (int k = 0; k < PER; ++k) {
-                if (ys[k] == xs[k]) act &= ~(1u << k);
+                more |= ys[k] != xs[k];
                 xs[k] = ys[k];
             }
         }
@@ -769,13 +785,17 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
         const int p = k * NT + threadIdx.x;
         const int q = p + (dir == 0 ? 1 : dir == 1 ? TX : TX * TY);
         const uint32_t za = zl[p], zb = zl[q];
-        const uint64_t ka = lkey<PB>(hk, p), kb = lkey<PB>(hk, q);
-        const uint64_t ks = kb < ka ? ka : kb;  // the upper end is the saddle
+        // the upper end is the saddle: q follows p in tile order, so q unless
+        // p's value key is the larger (32-bit work; the tile key is assembled once)
+        const uint32_t ha = hk[p], hb = hk[q];
+        const bool qup = hb >= ha;
+        const uint32_t hs = qup ? hb : ha, ps = qup ? (uint32_t)q : (uint32_t)p;
         if (tabled) {
-            insert((ks << (2 * ZB)) | min(za, zb) | ((uint64_t)max(za, zb) << ZB));
+            // (tile key << 2 ZB) | lo | hi << ZB, the tile key being (hs << PB) | ps
+            insert(((uint64_t)hs << (PB + 2 * ZB)) | (ps << (2 * ZB)) | min(za, zb) | (max(za, zb) << ZB));
         } else {
             tc.add(C_TAB_DIRECT);
-            lds_merge<VOL, CNT>(TL, hk, mh, za, ks, zb, cnt, cap, err, tc);
+            lds_merge<VOL, CNT>(TL, hk, mh, za, ((uint64_t)hs << PB) | ps, zb, cnt, cap, err, tc);
         }
     }
     __syncthreads();
@@ -820,16 +840,16 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
         const uint64_t t = lds_ld64(TL + i);
         uint32_t x = L::tgt(t);
         if (x == i) continue;
-        const uint64_t ks = L::key(t);
+        const uint64_t above = t | L::TM;  // a word lies above it exactly when its key is above t's
         for (uint32_t step = 0; step < cap; ++step) {
             const uint64_t tx = lds_ld64(TL + x);
             const uint32_t v = L::tgt(tx);
             if (v >= cnt) { err |= ST_CORRUPT; break; }
-            if (v == x || L::key(tx) > ks) break;
+            if (v == x || tx > above) break;
             x = v;
         }
         if (x != L::tgt(t))
-            __hip_atomic_store(TL + i, L::make(ks, x), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_store(TL + i, (t & ~L::TM) | x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
     if (threadIdx.x == 63) sb0 = gbase;
     __syncthreads();
@@ -855,13 +875,13 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
     // (the PER chases of a lane advance together, so their loads overlap)
     {
         uint32_t xs[PER], act = 0;
-        uint64_t lv[PER];
+        uint64_t lv[PER];  // a triplet word above this has its saddle above the vertex's level
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
             const int p = k * NT + threadIdx.x;
             const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
             xs[k] = zl[p];
-            lv[k] = lkey<PB>(hk, p);
+            lv[k] = (lkey<PB>(hk, p) << L::TB) | L::TM;
             if (!valid(lx, ly, lz)) { xs[k] = 0; continue; }
             if (xs[k] >= cnt) { err |= ST_CORRUPT; xs[k] = 0; continue; }
             act |= 1u << k;
@@ -877,7 +897,7 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
                 if (!((act >> k) & 1u)) continue;
                 const uint32_t v = L::tgt(t[k]);
                 if (v >= cnt) { err |= ST_CORRUPT; act &= ~(1u << k); continue; }
-                if (v == xs[k] || L::key(t[k]) > lv[k]) act &= ~(1u << k);
+                if (v == xs[k] || t[k] > lv[k]) act &= ~(1u << k);
                 else xs[k] = v;
             }
         }
@@ -1893,11 +1913,15 @@ __global__ __launch_bounds__(kBlock) void k_scatter(BwdGroup g, const int64_t *_
             const int mid = (lo + hi) >> 1;
             if (spo[mid] <= k) lo = mid; else hi = mid;
         }
+        // a zero upstream gradient adds nothing: its scattered read-modify-write is skipped (a loss
+        // that selects pairs, like a persistence threshold, leaves most of them at zero)
+        const float b_g = gb[k], d_g = gd[k];
+        if (b_g == 0.0f && d_g == 0.0f) continue;
         const int64_t vo = g.voff[lo];
         const uint32_t bk = birth[k], dk = death[k];
         if ((int64_t)bk >= g.nv[lo] || (int64_t)dk >= g.nv[lo]) continue;  // not an id of this field
-        grad[vo + bk] += gb[k];
-        unsafeAtomicAdd(grad + vo + dk, gd[k]);
+        if (b_g != 0.0f) grad[vo + bk] += b_g;
+        if (d_g != 0.0f) unsafeAtomicAdd(grad + vo + dk, d_g);
     }
 }
 
