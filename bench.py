@@ -526,6 +526,27 @@ def bench_backward(dev, mt, steps: int = 100):
         with torch.no_grad():
             flat -= lr * x.grad
     ks = mt.profile_end()
+    # the adjoint alone, called the way the autograd function calls it: host
+    # time to enqueue (the rest of loss.backward() is the loss's own backward
+    # ops and the autograd engine)
+    P_last = pairs[-1]
+    gb = torch.ones(P_last, dtype=torch.float32, device=dev)
+    gd = torch.ones(P_last, dtype=torch.float32, device=dev)
+    grad = torch.empty(plan.n_total, dtype=torch.float32, device=dev)
+    lib = mt.load_library()
+    st = torch.cuda.current_stream(dev).cuda_stream
+    b_ids, d_ids, offs = plan.birth, plan.death, plan.pair_offsets
+    torch.cuda.synchronize()
+    t_host = []
+    for _ in range(20):
+        h0 = time.perf_counter()
+        rc = lib.mt_pairs_backward(plan._dims_c, len(plan.dims), offs.data_ptr(), P_last, b_ids.data_ptr(),
+                                   d_ids.data_ptr(), gb.data_ptr(), gd.data_ptr(), grad.data_ptr(), 0, st)
+        t_host.append((time.perf_counter() - h0) * 1e6)
+        if rc != 0:
+            raise mt.MTError(rc, "mt_pairs_backward")
+    torch.cuda.synchronize()
+    adjoint_call_host_us = statistics.median(t_host)
     kern = {k: ks[k] for k in ("k_fill0", "k_scatter") if k in ks}
     kern_us = sum(v[0] for v in kern.values()) / steps * 1e3
     P = statistics.median(pairs)
@@ -540,6 +561,7 @@ def bench_backward(dev, mt, steps: int = 100):
         "pairs_median": P,
         "bwd_us_median": statistics.median(bwd_us[2:]),
         "bwd_host_us_median": statistics.median(host_bwd_us[2:]),
+        "adjoint_call_host_us": adjoint_call_host_us,
         "bwd_kernel_us": kern_us,
         "bwd_kernels": {k: {"avg_us": v[0] / v[1] * 1e3, "launches": v[1]} for k, v in kern.items()},
         "adjoint_roofline": {"bound": "hbm", "bytes": adj_bytes, "achieved_GBps": adj_bytes / (kern_us * 1e3),
