@@ -825,11 +825,90 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
     }
     __syncthreads();
     phase(C_PH_COMPACT);
-    const uint32_t nw = nwin;
-    for (uint32_t i = threadIdx.x; i < nw; i += NT) {
-        const uint64_t e = htab[i];
-        const uint32_t tag = (uint32_t)(e & TAGM);
-        lds_merge<VOL, CNT>(TL, hk, mh, tag & (ZMAX - 1), e >> (2 * ZB), tag >> ZB, cnt, cap, err, tc);
+    // The table's merges (Alg. 3), the same steps as lds_merge written as one
+    // step per loop round: each wave takes an equal share of the entries, and
+    // a lane whose merge has ended takes the wave's next entry at once.  The
+    // wave then loops about as often as its lanes' steps add up to over 64,
+    // not as often as the longest merge of every batch of 64 (merges take 7
+    // steps on average and up to about 30).
+    {
+        const uint32_t nw = nwin;
+        const uint32_t share = (nw + NW - 1) / NW;
+        uint32_t next = min(nw, (uint32_t)wave * share);
+        const uint32_t end = min(nw, next + share);
+        bool act = false;
+        uint32_t u = 0, v = 0, steps = 0;
+        uint64_t tu = 0, tv = 0, ksT = 0;
+        for (;;) {
+            const uint64_t idle = __ballot(!act);
+            if (!act) {
+                const uint32_t i = next + (uint32_t)__popcll(idle & lanemask_lt());
+                if (i < end) {
+                    const uint64_t e = htab[i];
+                    const uint32_t tag = (uint32_t)(e & TAGM);
+                    u = tag & (ZMAX - 1);
+                    v = tag >> ZB;
+                    ksT = (e >> (2 * ZB)) << L::TB;
+                    tc.add(C_LDS_MERGES);
+                    if (u >= cnt || v >= cnt) {
+                        err |= ST_CORRUPT;
+                    } else {
+                        tu = lds_ld64(TL + u);
+                        tv = lds_ld64(TL + v);
+                        steps = 0;
+                        act = true;
+                    }
+                }
+            }
+            next += (uint32_t)__popcll(idle);
+            if (__ballot(act) == 0ull) break;
+            if (!act) continue;
+            ++steps;
+            const uint32_t u1 = L::tgt(tu), v1 = L::tgt(tv);
+            const bool du = u1 != u && tu < ksT;
+            const bool dv = v1 != v && tv < ksT;
+            if (u1 >= cnt || v1 >= cnt) {
+                err |= ST_CORRUPT;
+                act = false;
+            } else if (du || dv) {
+                const uint32_t x = du ? u1 : v1;
+                const uint64_t t = lds_ld64(TL + x);
+                if (du) { u = x; tu = t; } else { v = x; tv = t; }
+            } else if (u == v) {
+                act = false;
+            } else {
+                const uint32_t pu = mh[u], pv = mh[v];
+                const uint32_t ku = hk[pu], kv = hk[pv];
+                if (kv < ku || (kv == ku && pv < pu)) {
+                    const uint32_t w = u; u = v; v = w;
+                    const uint64_t tw = tu; tu = tv; tv = tw;
+                }
+                uint64_t seen = tv;
+                tc.add(C_LDS_CAS);
+                if (__hip_atomic_compare_exchange_strong(TL + v, &seen, ksT | u, __ATOMIC_RELAXED,
+                                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) {
+                    if (L::tgt(tv) == v) {
+                        act = false;
+                    } else {
+                        ksT = tv & ~L::TM;
+                        v = L::tgt(tv);
+                        tv = lds_ld64(TL + v);
+                    }
+                } else {
+                    tc.add(C_LDS_CAS_FAIL);
+                    tv = seen;
+                }
+                if (act) tu = lds_ld64(TL + u);
+            }
+            if (act && steps == cap) {
+                err |= ST_LIVELOCK;
+                act = false;
+            }
+            if (!act) {
+                tc.add(C_LDS_STEPS, steps);
+                tc.max(C_LDS_MAX_STEPS, steps);
+            }
+        }
     }
     __syncthreads();
     phase(C_PH_MERGE);
