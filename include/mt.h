@@ -424,7 +424,7 @@ int mt_get_table_probes(void);
  *
  * mt_read_counters synchronizes `stream` and copies the counters of the last
  * build on `workspace` into counts (host, uint64[n]); it returns how many it
- * wrote (at most 28; the rest of counts is zeroed) or an error.  In order:
+ * wrote (at most 29; the rest of counts is zeroed) or an error.  In order:
  *   0 cross-tile merges started (one per queued fact)
  *   1 iterations of the cross-tile merge loop (Alg. 3)
  *   2 of those, descent steps
@@ -439,7 +439,8 @@ int mt_get_table_probes(void);
  *  11 most iterations of a single in-tile merge
  *  12 in-tile edges offered to the table of basin pairs
  *  13 table probes (one LDS atomic minimum each)
- *  14 in-tile edges merged without the table
+ *  14 in-tile edges that found no room in the table (they go to a short
+ *     overflow list) or had no table (merged at once)
  *  15 chase steps of the output pass (Alg. 4 for every regular vertex)
  *  16 path compressions in long cross-tile descents (a link re-pointed past
  *     the next one when that one's saddle is not higher, one Repair step)
@@ -452,6 +453,8 @@ int mt_get_table_probes(void);
  *     to the local minima; clearing the pair table; edges offered to the
  *     table; compaction of the table; the in-tile merges; repair of the
  *     local minima; minimum records and vertex labels
+ *  28 tiles whose overflow list filled up, so that every edge of the tile
+ *     was merged at once after the table's merges
  * Only a counting build writes them; after a timed build they read 0.
  */
 int mt_set_counting(int on);

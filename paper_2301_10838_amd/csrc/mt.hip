@@ -368,11 +368,12 @@ static int launch_local(const Plan &p, const ClassLaunch &cl, const Ptrs &w, con
                         hipStream_t st)
 {
     // a table-probe bound below the maximum only matters to tests of the
-    // fallback paths: its instantiation (timed kernel only) checks the bound
+    // fallback paths: the counting build always checks it, and of the
+    // timed kernel an instantiation of its own does
+    if (p.count == 1) return launch_local_as<S, 1, true>(p, cl, w, f, flip, st);
     if (p.probes < (uint32_t)kMaxProbes) return launch_local_as<S, 0, true>(p, cl, w, f, flip, st);
     if (p.count == 2) return launch_local_as<S, 2, false>(p, cl, w, f, flip, st);
-    return p.count ? launch_local_as<S, 1, false>(p, cl, w, f, flip, st)
-                   : launch_local_as<S, 0, false>(p, cl, w, f, flip, st);
+    return launch_local_as<S, 0, false>(p, cl, w, f, flip, st);
 }
 
 template <class S>

@@ -119,7 +119,7 @@ enum CtrId {
     C_LDS_MAX_STEPS,  // most iterations of one in-tile merge (a maximum)
     C_TAB_INSERTS,    // edges offered to the in-tile pair table
     C_TAB_PROBES,     // atomic-min probes of those inserts
-    C_TAB_DIRECT,     // edges merged without the table (no room, or no table)
+    C_TAB_DIRECT,     // edges without table room (overflow list), or without a table (merged at once)
     C_REG_CHASES,     // chase steps of the output pass
     C_GM_COMPRESS,    // path compressions in cross-tile descents
     C_MIN_CHASES,     // chase steps of the minimum repair
@@ -136,6 +136,7 @@ enum CtrId {
     C_PH_MERGE,       // merges of the kept edges (Alg. 3 in LDS)
     C_PH_REPAIR,      // repair of the local minima (Alg. 5)
     C_PH_LABEL,       // minimum records written, vertices labelled
+    C_TAB_REDO,       // tiles whose overflow list filled up (all their edges merged at once)
     kCtr
 };
 __host__ __device__ constexpr bool ctr_is_max(int i) { return i == C_GM_MAX_STEPS || i == C_LDS_MAX_STEPS; }
@@ -539,7 +540,11 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
     i16a *const wl = (i16a *)htab;  // lowest lower neighbour in the tile (self at a local minimum)
     static_assert(sizeof(int16_t) * VOL <= sizeof(uint64_t) * H, "aliasing");
     __shared__ uint32_t wsum[VOL / 64];
-    __shared__ uint32_t sb0, nwin, scnt;
+    __shared__ uint32_t sb0, nwin, scnt, novf;
+    // edges that found no table room, merged with the table's entries (a
+    // count above kOvf sends the tile down the direct path instead)
+    constexpr uint32_t kOvf = 64;
+    __shared__ uint64_t ovf[kOvf];
 
     const int64_t tl = xcd_tile(blockIdx.x, gridDim.x, remap);
     if (tl >= ntiles) return;
@@ -666,6 +671,7 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
                 // into a wave-wide one whose result it must wait for at once)
                 gbase = atomicAdd(&h->n_minima + (threadIdx.x - 63u), inc);
                 nwin = 0;
+                novf = 0;
             }
         }
         __syncthreads();
@@ -676,7 +682,6 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
             const uint32_t r = wsum[k * NW + wave] + (uint32_t)__popcll(mb[k] & lanemask_lt());
             zl[p] = (uint16_t)r;
             mh[r] = (uint16_t)p;
-            TL[r] = L::make(lkey<PB>(hk, p), r);
         }
     }
     __syncthreads();  // the basin pass reads the minima's numbers
@@ -729,18 +734,25 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
     // edges joining the same two basins only the lowest (smallest upper end)
     // is merged: the connection it makes at its level implies the connection
     // every other one would make at a higher level.  The pair table keeps that
-    // lowest edge; an edge that finds no table room is merged directly, and so
-    // is every edge of a tile with more minima than a tag can number.
+    // lowest edge; an edge that finds no table room goes to a short overflow
+    // list merged with the table's entries (should that list fill up too,
+    // every edge of the tile is merged directly once the table's merges are
+    // done), and every edge of a tile with more minima than a tag can number
+    // is merged directly.
     uint32_t err = 0;
     const bool tabled = (uint32_t)HALF <= ZMAX || cnt <= ZMAX;
+    // the local minima's triplets: roots at their own level
+    auto init_tl = [&]() {
+        for (uint32_t i = threadIdx.x; i < cnt; i += NT) TL[i] = L::make(lkey<PB>(hk, mh[i]), i);
+    };
     // One atomic min per probe: an empty entry is claimed; an entry of the
     // same pair keeps the lower edge; an entry of another pair keeps the
     // lower of the two words and the lane carries the other one on.  Entries
     // move but are never dropped, so every pair's lowest edge ends in the
-    // table (or is merged directly); a pair left with a second, higher entry
-    // only costs a merge that changes nothing.  `probes` (at most 32 by
-    // default) bounds the probes before the direct merge; a smaller value only
-    // sends more edges down that path.
+    // table (or on the overflow list); a pair left with a second, higher
+    // entry only costs a merge that changes nothing.  `probes` (at most 32 by
+    // default) bounds the probes before the overflow list; a smaller value
+    // only sends more edges down that path.
     // (The probe loops have a compile-time length and are unrolled: measurably
     // faster than a loop to a runtime bound.  With the default bound, the
     // maximum, the kernel is instantiated without any bound check (LIMIT
@@ -760,50 +772,83 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
             si = (si + 1) & (H - 1);
         }
         tc.add(C_TAB_DIRECT);
-        const uint32_t tag = (uint32_t)(val & TAGM);
-        lds_merge<VOL, CNT>(TL, hk, mh, tag & (ZMAX - 1), val >> (2 * ZB), tag >> ZB, cnt, cap, err, tc);
+        const uint32_t o = atomicAdd(&novf, 1u);
+        if (o < kOvf) ovf[o] = val;
     };
-    // A lane first marks which of its (vertex, direction) slots hold such an
-    // edge, then inserts one marked slot per round: a wave runs as many rounds
-    // as its busiest lane has edges, not one per slot.
-    static_assert(PER * 3 <= 32, "slot marks fit one word");
-    uint32_t pend = 0;
-#pragma unroll
-    for (int k = 0; k < PER; ++k) {
+    // The edge from p in direction dir (0: +x, 1: +y, 2: +z) to q: its upper
+    // end is the saddle, q unless p's value key is the larger (q follows p in
+    // tile order; 32-bit work, the tile key is assembled once).  Into the
+    // table, or merged at once (`direct`, and in a tile with more minima than
+    // a tag numbers).
+    auto offer = [&](int p, int dir, bool direct) {
+        const int q = p + (dir == 0 ? 1 : dir == 1 ? TX : TX * TY);
+        const uint32_t za = zl[p], zb = zl[q];
+        const uint32_t ha = hk[p], hb = hk[q];
+        const bool qup = hb >= ha;
+        const uint32_t hs = qup ? hb : ha, ps = qup ? (uint32_t)q : (uint32_t)p;
+        if (tabled && !direct) {
+            // (tile key << 2 ZB) | lo | hi << ZB, the tile key being (hs << PB) | ps
+            insert(((uint64_t)hs << (PB + 2 * ZB)) | (ps << (2 * ZB)) | min(za, zb) | (max(za, zb) << ZB));
+        } else {
+            if (!tabled) tc.add(C_TAB_DIRECT);  // (the edges of an overflowing tile were counted on the way in)
+            lds_merge<VOL, CNT>(TL, hk, mh, za, ((uint64_t)hs << PB) | ps, zb, cnt, cap, err, tc);
+        }
+    };
+    // Slot (k, dir) of a lane holds such an edge: vertex k of the lane and its
+    // +dir neighbour lie in the tile and in different local basins.
+    auto marked = [&](int k, int dir) {
         const int p = k * NT + threadIdx.x;
         const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
-        if (!valid(lx, ly, lz)) continue;
-        const uint32_t za = zl[p];
-        if (lx + 1 < c.ex && zl[p + 1] != za) pend |= 1u << (3 * k);
-        if (ly + 1 < c.ey && zl[p + TX] != za) pend |= 1u << (3 * k + 1);
-        if (lz + 1 < c.ez && zl[p + TX * TY] != za) pend |= 1u << (3 * k + 2);
+        if (!valid(lx, ly, lz)) return false;
+        if (dir == 0) return lx + 1 < c.ex && zl[p + 1] != zl[p];
+        if (dir == 1) return ly + 1 < c.ey && zl[p + TX] != zl[p];
+        return lz + 1 < c.ez && zl[p + TX * TY] != zl[p];
+    };
+    // Each wave lists its marked slots in LDS (in the space of the minima's
+    // triplets, which are only written once the table is complete) and its
+    // lanes take the list's entries in turn: a wave runs as many rounds as
+    // its edges over 64, not as many as its busiest lane has (about 6 against
+    // 10 on a log-normal field).  Slots past the list's room stay with their
+    // lanes, one per round.
+    constexpr uint32_t kListCap = HALF * (uint32_t)(sizeof(uint64_t) / sizeof(uint16_t)) / NW;
+    static_assert(PB + 2 <= 16 && PER * 3 <= 32, "list codes and slot marks");
+    uint16_t *const elist = reinterpret_cast<uint16_t *>(TL) + wave * kListCap;
+    const uint32_t lcap = tabled ? kListCap : 0u;  // untabled tiles merge at once and need the triplets
+    uint32_t pend = 0, nlist = 0;                  // slots left to their lanes; listed slots (uniform)
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+#pragma unroll
+        for (int dir = 0; dir < 3; ++dir) {
+            const bool m = marked(k, dir);
+            const uint64_t bm = __ballot(m);
+            if (m) {
+                const uint32_t pos = nlist + (uint32_t)__popcll(bm & lanemask_lt());
+                if (pos < lcap) elist[pos] = (uint16_t)((k * NT + threadIdx.x) | (dir << PB));
+                else pend |= 1u << (3 * k + dir);
+            }
+            nlist += (uint32_t)__popcll(bm);
+        }
+    }
+    if (!tabled) init_tl();
+    __syncthreads();
+    const uint32_t nl = min(nlist, lcap);
+    for (uint32_t i = lane; i < nl; i += 64) {
+        const uint32_t code = elist[i];
+        offer((int)(code & (VOL - 1)), (int)(code >> PB), false);
     }
     while (pend) {
         const int b = __builtin_ctz(pend);
         pend &= pend - 1;
-        const int k = b / 3, dir = b - 3 * k;
-        const int p = k * NT + threadIdx.x;
-        const int q = p + (dir == 0 ? 1 : dir == 1 ? TX : TX * TY);
-        const uint32_t za = zl[p], zb = zl[q];
-        // the upper end is the saddle: q follows p in tile order, so q unless
-        // p's value key is the larger (32-bit work; the tile key is assembled once)
-        const uint32_t ha = hk[p], hb = hk[q];
-        const bool qup = hb >= ha;
-        const uint32_t hs = qup ? hb : ha, ps = qup ? (uint32_t)q : (uint32_t)p;
-        if (tabled) {
-            // (tile key << 2 ZB) | lo | hi << ZB, the tile key being (hs << PB) | ps
-            insert(((uint64_t)hs << (PB + 2 * ZB)) | (ps << (2 * ZB)) | min(za, zb) | (max(za, zb) << ZB));
-        } else {
-            tc.add(C_TAB_DIRECT);
-            lds_merge<VOL, CNT>(TL, hk, mh, za, ((uint64_t)hs << PB) | ps, zb, cnt, cap, err, tc);
-        }
+        const int k = b / 3;
+        offer(k * NT + threadIdx.x, b - 3 * k, false);
     }
     __syncthreads();
     phase(C_PH_INSERT);
     // Occupied entries, compacted to the front of the table so that every
     // lane of a wave has a merge: each lane holds its entries while the
-    // table is rewritten.
+    // table is rewritten.  The triplets take the lists' place.
     {
+        if (tabled) init_tl();
         constexpr int PER = (H + NT - 1) / NT;
         uint64_t e[PER];
         uint32_t pos[PER];
@@ -831,11 +876,13 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
     // wave then loops about as often as its lanes' steps add up to over 64,
     // not as often as the longest merge of every batch of 64 (merges take 7
     // steps on average and up to about 30).
+    // The overflow list's edges follow the table's entries.
+    const uint32_t nov = novf;
     {
-        const uint32_t nw = nwin;
-        const uint32_t share = (nw + NW - 1) / NW;
-        uint32_t next = min(nw, (uint32_t)wave * share);
-        const uint32_t end = min(nw, next + share);
+        const uint32_t nw = nwin, ne = nw + min(nov, kOvf);
+        const uint32_t share = (ne + NW - 1) / NW;
+        uint32_t next = min(ne, (uint32_t)wave * share);
+        const uint32_t end = min(ne, next + share);
         bool act = false;
         uint32_t u = 0, v = 0, steps = 0;
         uint64_t tu = 0, tv = 0, ksT = 0;
@@ -844,7 +891,7 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
             if (!act) {
                 const uint32_t i = next + (uint32_t)__popcll(idle & lanemask_lt());
                 if (i < end) {
-                    const uint64_t e = htab[i];
+                    const uint64_t e = i < nw ? htab[i] : ovf[i - nw];
                     const uint32_t tag = (uint32_t)(e & TAGM);
                     u = tag & (ZMAX - 1);
                     v = tag >> ZB;
@@ -909,6 +956,14 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
                 tc.max(C_LDS_MAX_STEPS, steps);
             }
         }
+    }
+    if (nov > kOvf) {  // (uniform) the overflow list ran out of room: every edge is merged at once
+        if (threadIdx.x == 0) tc.add(C_TAB_REDO);
+#pragma unroll
+        for (int k = 0; k < PER; ++k)
+#pragma unroll
+            for (int dir = 0; dir < 3; ++dir)
+                if (marked(k, dir)) offer(k * NT + threadIdx.x, dir, true);
     }
     __syncthreads();
     phase(C_PH_MERGE);

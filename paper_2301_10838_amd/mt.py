@@ -44,7 +44,7 @@ COUNTER_NAMES = [
     "lds_merges", "lds_steps", "lds_cas", "lds_cas_fail", "lds_max_steps",
     "table_inserts", "table_probes", "table_direct", "output_chase_steps", "gm_compress", "min_chase_steps",
     "cyc_load", "cyc_descent", "cyc_number", "cyc_basin", "cyc_clear", "cyc_insert", "cyc_compact", "cyc_merge",
-    "cyc_repair", "cyc_label",
+    "cyc_repair", "cyc_label", "table_overflow_tiles",
 ]
 
 # tree kinds (include/mt.h)

@@ -8,8 +8,9 @@ and the step cap, all through the C ABI and bit-exact against the oracle.
   in sublevel volume discussed for the Richtmyer-Meshkov data, Sec. 4), with
   and without tiny noise on the plateau; nested exact-tie plateaus.
 - The LDS pair tables (lowest edge per pair of basins, in a tile and across a
-  tile face) limited to 0 or 1 probe, so that the direct-merge path inside the
-  tile and the as-is queueing across tiles carry most or all edges.
+  tile face) limited to 0, 1, 2 or 4 probes, so that the overflow list and
+  the direct merges inside the tile and the as-is queueing across tiles carry
+  many or all edges.
 - The step cap set to 1 from the host: every kernel leaves its bounded loops
   and the call reports MT_ERR_LIVELOCK; with the cap restored the same
   process gets the oracle's tree.
@@ -68,7 +69,7 @@ PROBE_CASES = [
 ]
 
 
-@pytest.mark.parametrize("probes", [0, 1])
+@pytest.mark.parametrize("probes", [0, 1, 2, 4])
 @pytest.mark.parametrize("name,maker", PROBE_CASES, ids=[a[0] for a in PROBE_CASES])
 def test_table_fallbacks(dev, restore_config, name, maker, probes):
     import paper_2301_10838_amd.mt as mt

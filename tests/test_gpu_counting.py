@@ -57,3 +57,36 @@ def test_counting_build_same_tree_and_consistent_counts(name, maker):
     # a timed build after it leaves the counters at zero
     mt.mt_build(ft, workspace=ws)
     assert all(v == 0 for v in mt.read_counters(ws).values())
+
+
+@pytest.mark.parametrize("probes", [0, 2])
+def test_counting_overflow_paths(probes):
+    """A probe limit sends edges past the in-tile pair table: with no probe
+    every offered edge overflows and every tile with more edges than the
+    overflow list holds merges all its edges at once; with two probes some
+    edges overflow.  The tree stays the oracle's either way."""
+    import paper_2301_10838_amd.mt as mt
+
+    dev = device()
+    f = fields.lognormal_grf((64, 64, 64), 113)
+    print("case counting overflow probes", probes, flush=True)
+    ft = torch.from_numpy(f).to(dev)
+    ws = mt.alloc_workspace(mt.workspace_bytes(f.shape), dev)
+    mt.set_table_probes(probes)
+    mt.set_counting(True)
+    try:
+        T = mt.mt_build(ft, workspace=ws)
+        c = mt.read_counters(ws)
+        b, d, bv, dv, r = mt.mt_persistence_pairs(ft, T, workspace=ws)
+        torch.cuda.synchronize()
+    finally:
+        mt.set_counting(False)
+        mt.set_table_probes(-1)
+    assert_matches_oracle(f, u32(T).reshape(-1, 2), (u32(b), u32(d), bv.cpu().numpy(), dv.cpu().numpy(), r),
+                          f"overflow probes={probes}")
+    assert c["table_direct"] > 0
+    if probes == 0:
+        assert c["table_probes"] == 0 and c["table_direct"] == c["table_inserts"]
+        assert 0 < c["table_overflow_tiles"] <= 64  # 64 tiles of 16^3, each with hundreds of edges
+    else:
+        assert c["table_direct"] < c["table_inserts"]
