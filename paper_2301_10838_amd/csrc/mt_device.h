@@ -615,20 +615,23 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
             wl[p] = (int16_t)p;
             continue;
         }
-        uint64_t best = lkey<PB>(hk, p);
+        // the six neighbours' keys read at once (an absent neighbour reads the
+        // vertex itself); the lowest (value key, position) wins, in 32-bit
+        // compares: the lower positions are taken in descending order and win
+        // ties, the higher ones in ascending order and lose them
+        const bool cmx = lx > 0, cmy = ly > 0, cmz = lz > 0;
+        const bool cpx = lx + 1 < c.ex, cpy = ly + 1 < c.ey, cpz = lz + 1 < c.ez;
+        const uint32_t h0 = hk[p];
+        const uint32_t hmx = hk[cmx ? p - 1 : p], hmy = hk[cmy ? p - TX : p], hmz = hk[cmz ? p - TX * TY : p];
+        const uint32_t hpx = hk[cpx ? p + 1 : p], hpy = hk[cpy ? p + TX : p], hpz = hk[cpz ? p + TX * TY : p];
+        uint32_t bh = h0;
         int bp = p;
-#define MT_CAND(cond, q)                                                                    \
-        if (cond) {                                                                         \
-            const uint64_t kq = lkey<PB>(hk, (q));                                          \
-            if (kq < best) { best = kq; bp = (q); }                                        \
-        }
-        MT_CAND(lx > 0, p - 1)
-        MT_CAND(lx + 1 < c.ex, p + 1)
-        MT_CAND(ly > 0, p - TX)
-        MT_CAND(ly + 1 < c.ey, p + TX)
-        MT_CAND(lz > 0, p - TX * TY)
-        MT_CAND(lz + 1 < c.ez, p + TX * TY)
-#undef MT_CAND
+        if (cmx && hmx <= bh) { bh = hmx; bp = p - 1; }
+        if (cmy && hmy <= bh) { bh = hmy; bp = p - TX; }
+        if (cmz && hmz <= bh) { bh = hmz; bp = p - TX * TY; }
+        if (cpx && hpx < bh) { bh = hpx; bp = p + 1; }
+        if (cpy && hpy < bh) { bh = hpy; bp = p + TX; }
+        if (cpz && hpz < bh) { bh = hpz; bp = p + TX * TY; }
         wl[p] = (int16_t)bp;
     }
     __syncthreads();
