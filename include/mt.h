@@ -424,7 +424,7 @@ int mt_get_table_probes(void);
  *
  * mt_read_counters synchronizes `stream` and copies the counters of the last
  * build on `workspace` into counts (host, uint64[n]); it returns how many it
- * wrote (at most 29; the rest of counts is zeroed) or an error.  In order:
+ * wrote (at most 30; the rest of counts is zeroed) or an error.  In order:
  *   0 cross-tile merges started (one per queued fact)
  *   1 iterations of the cross-tile merge loop (Alg. 3)
  *   2 of those, descent steps
@@ -455,6 +455,9 @@ int mt_get_table_probes(void);
  *     local minima; minimum records and vertex labels
  *  28 tiles whose overflow list filled up, so that every edge of the tile
  *     was merged at once after the table's merges
+ *  29 rounds of the output pass's chase loop, summed over waves and vertex
+ *     groups (a wave's round issues the next step of all its lanes' chases;
+ *     counter 15 over 256 times this is the share of chase slots in use)
  * Only a counting build writes them; after a timed build they read 0.
  */
 int mt_set_counting(int on);

@@ -137,6 +137,7 @@ enum CtrId {
     C_PH_REPAIR,      // repair of the local minima (Alg. 5)
     C_PH_LABEL,       // minimum records written, vertices labelled
     C_TAB_REDO,       // tiles whose overflow list filled up (all their edges merged at once)
+    C_REG_ROUNDS,     // rounds of the output pass's chase loop, per wave and vertex group
     kCtr
 };
 __host__ __device__ constexpr bool ctr_is_max(int i) { return i == C_GM_MAX_STEPS || i == C_LDS_MAX_STEPS; }
@@ -1659,6 +1660,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
         for (uint32_t step = 0; act != 0; ++step) {
             if (step == cap) { err |= ST_LIVELOCK; break; }
             tc.add(C_REG_CHASES, (uint32_t)__builtin_popcount(act));
+            if constexpr (CNT) tc.add(C_REG_ROUNDS, (__ballot(1) & lanemask_lt()) == 0ull);  // first active lane
             // all RV loads issued together, no branch around them: a vertex
             // whose chase has ended reads slot 0 (one shared line per wave)
 #pragma unroll

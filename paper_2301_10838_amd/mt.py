@@ -45,6 +45,7 @@ COUNTER_NAMES = [
     "table_inserts", "table_probes", "table_direct", "output_chase_steps", "gm_compress", "min_chase_steps",
     "cyc_load", "cyc_descent", "cyc_number", "cyc_basin", "cyc_clear", "cyc_insert", "cyc_compact", "cyc_merge",
     "cyc_repair", "cyc_label", "table_overflow_tiles",
+    "output_chase_rounds",
 ]
 
 # tree kinds (include/mt.h)
