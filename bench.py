@@ -64,7 +64,7 @@ MODEL_BYTES_PER_VERTEX = {
     "k_repair_min": 0,   # per-minimum term below
     "k_repair_reg": 16,  # read label and f, write the triplet
     "k_pairs_count": 8,  # read the triplet
-    "k_pairs_write": 8,  # read the triplet (+24 per pair: both values read, the pair written)
+    "k_pairs_write": 0,  # staged readout after a build: per-pair and per-bucket terms below
 }
 
 
@@ -82,7 +82,8 @@ def model_bytes(kernel: str, n_vertices: int, n_pairs: int, n_local_minima: int,
     if kernel == "k_repair_min":
         b += 16 * n_local_minima   # read (and rewrite) every slot once
     if kernel == "k_pairs_write":
-        b += 24 * n_pairs          # f at birth and death read; birth, death ids and values written
+        # the staged pair (ids and value bits) read and written; one count byte per 64 vertices
+        b += 32 * n_pairs + n_vertices // 64
     return float(b)
 
 

@@ -55,4 +55,4 @@ def test_face_edges_and_algorithmic_bytes():
     assert bench.model_bytes("k_repair_reg", N, P, M) == 16 * N
     assert bench.model_bytes("k_merge_q", N, P, M, Q) == 16 * Q + 16 * M
     assert bench.model_bytes("k_cross", N, P, M, Q, F) == 16 * F + 16 * Q
-    assert bench.model_bytes("k_pairs_write", N, P, M) == 8 * N + 24 * P
+    assert bench.model_bytes("k_pairs_write", N, P, M) == 32 * P + N // 64
