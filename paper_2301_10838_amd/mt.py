@@ -464,7 +464,9 @@ class MergeTreePairs(torch.autograd.Function):
         ctx.plan = plan
         ctx.P = P
         # the plan's buffers are reused by the next forward: keep this pairing
-        ctx.save_for_backward(plan.birth[:P].clone(), plan.death[:P].clone(), plan.pair_offsets.clone())
+        # (private copies, neither inputs nor outputs of the function, so they
+        # are kept on ctx directly: save_for_backward's checks cost host time)
+        ctx.pairing = (plan.birth[:P].clone(), plan.death[:P].clone(), plan.pair_offsets.clone())
         return plan.bval[:P].clone(), plan.dval[:P].clone()
 
     @staticmethod
@@ -479,7 +481,7 @@ class MergeTreePairs(torch.autograd.Function):
             g_death = torch.zeros(P, dtype=torch.float32, device=dev)
         gb = g_birth.contiguous().float()
         gd = g_death.contiguous().float()
-        birth, death, offsets = ctx.saved_tensors
+        birth, death, offsets = ctx.pairing
         grad = torch.empty(plan.n_total, dtype=torch.float32, device=dev)
         _check(load_library().mt_pairs_backward(plan._dims_c, len(plan.dims), offsets.data_ptr(), P,
                                                 birth.data_ptr(), death.data_ptr(), gb.data_ptr(), gd.data_ptr(),
