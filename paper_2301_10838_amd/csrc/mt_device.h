@@ -746,8 +746,19 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
     uint32_t err = 0;
     const bool tabled = (uint32_t)HALF <= ZMAX || cnt <= ZMAX;
     // the local minima's triplets: roots at their own level
+    // The value keys of the local minima, for the table merges' test of
+    // which minimum lies deeper, where a tile with a table (at most ZMAX
+    // minima) leaves the triplets' upper half unused (shapes whose triplets
+    // have no such half read them through the minima's positions).
+    constexpr bool MKV = (uint32_t)HALF > ZMAX;
+    static_assert(!MKV || 2 * (HALF - ZMAX) >= ZMAX, "room for the minima's value keys");
+    uint32_t *const mkv = reinterpret_cast<uint32_t *>(TL + (MKV ? ZMAX : 0));
     auto init_tl = [&]() {
-        for (uint32_t i = threadIdx.x; i < cnt; i += NT) TL[i] = L::make(lkey<PB>(hk, mh[i]), i);
+        for (uint32_t i = threadIdx.x; i < cnt; i += NT) {
+            const uint32_t mp = mh[i];
+            TL[i] = L::make(lkey<PB>(hk, mp), i);
+            if (MKV && tabled) mkv[i] = hk[mp];
+        }
     };
     // One atomic min per probe: an empty entry is claimed; an entry of the
     // same pair keeps the lower edge; an entry of another pair keeps the
@@ -893,7 +904,8 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
         for (;;) {
             const uint64_t idle = __ballot(!act);
             if (!act) {
-                const uint32_t i = next + (uint32_t)__popcll(idle & lanemask_lt());
+                const uint32_t i = next + __builtin_amdgcn_mbcnt_hi((uint32_t)(idle >> 32),
+                                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)idle, 0u));
                 if (i < end) {
                     const uint64_t e = i < nw ? htab[i] : ovf[i - nw];
                     const uint32_t tag = (uint32_t)(e & TAGM);
@@ -928,9 +940,18 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
             } else if (u == v) {
                 act = false;
             } else {
-                const uint32_t pu = mh[u], pv = mh[v];
-                const uint32_t ku = hk[pu], kv = hk[pv];
-                if (kv < ku || (kv == ku && pv < pu)) {
+                // tile keys compared as (value key, position): positions only on a tie
+                bool swap;
+                if constexpr (MKV) {
+                    const uint32_t ku = mkv[u], kv = mkv[v];
+                    swap = kv < ku;
+                    if (kv == ku) swap = mh[v] < mh[u];
+                } else {
+                    const uint32_t pu = mh[u], pv = mh[v];
+                    const uint32_t ku = hk[pu], kv = hk[pv];
+                    swap = kv < ku || (kv == ku && pv < pu);
+                }
+                if (swap) {
                     const uint32_t w = u; u = v; v = w;
                     const uint64_t tw = tu; tu = tv; tv = tw;
                 }
