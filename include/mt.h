@@ -398,9 +398,10 @@ int mt_autotune_schedule(const float *fields, const int64_t *dims, int32_t n_fie
  *
  * mt_set_table_probes -- probes each edge may spend in the LDS tables that
  * keep only the lowest edge between two basins (inside a tile, and across a
- * tile face) before it takes the path that needs no table: merged directly
- * inside the tile, queued as it is across tiles.  Both paths give the same
- * triplets; the tables only save merges.  probes = -1 restores the default
+ * tile face) before it takes the path that needs no table: inside the tile
+ * a short overflow list merged with the table's entries (and, should that
+ * list fill up, every edge of the tile merged directly), across tiles queued
+ * as it is.  All paths give the same triplets; the tables only save merges.  probes = -1 restores the default
  * (32, also the largest value); 0 <= probes <= 32 sets it (0 sends every
  * edge down the direct path); anything else is MT_ERR_INVALID_ARG.
  * mt_get_table_probes returns it.

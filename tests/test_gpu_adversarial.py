@@ -9,7 +9,7 @@ and the step cap, all through the C ABI and bit-exact against the oracle.
   and without tiny noise on the plateau; nested exact-tie plateaus.
 - The LDS pair tables (lowest edge per pair of basins, in a tile and across a
   tile face) limited to 0, 1, 2 or 4 probes, so that the overflow list and
-  the direct merges inside the tile and the as-is queueing across tiles carry
+  the direct merges inside the tile, and the as-is queueing across tiles, carry
   many or all edges.
 - The step cap set to 1 from the host: every kernel leaves its bounded loops
   and the call reports MT_ERR_LIVELOCK; with the cap restored the same
