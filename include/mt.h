@@ -449,11 +449,13 @@ int mt_get_table_probes(void);
  *  18-27 (mode 2 only) shader clock cycles of the tile pass's phases,
  *     summed over tiles, each taken by the workgroup's first lane from one
  *     barrier to the next
- *     (so a phase includes the wait for its slowest wave): field loads;
- *     lowest lower neighbours; numbering of the local minima; descent chains
- *     to the local minima; clearing the pair table; edges offered to the
- *     table; compaction of the table; the in-tile merges; repair of the
- *     local minima; minimum records and vertex labels
+ *     (so a phase includes the wait for its slowest wave): field loads
+ *     awaited and order keys written; lowest lower neighbours; numbering of
+ *     the local minima; descent chains to the local minima; field loads
+ *     issued and the pair table cleared (from the workgroup's start, ahead
+ *     of the first barrier); edges offered to the table; compaction of the
+ *     table; the in-tile merges; repair of the local minima; minimum records
+ *     and vertex labels
  *  28 tiles whose overflow list filled up, so that every edge of the tile
  *     was merged at once after the table's merges
  *  29 rounds of the output pass's chase loop, summed over waves and vertex

@@ -126,11 +126,11 @@ enum CtrId {
     // shader clock cycles of each barrier-separated phase of the tile pass,
     // summed over tiles (taken by the workgroup's first lane, so each phase
     // includes the wait for its slowest wave)
-    C_PH_LOAD,        // field loads, order keys into LDS
+    C_PH_LOAD,        // field loads awaited, order keys into LDS
     C_PH_DESCENT,     // lowest lower neighbour of every vertex
     C_PH_NUMBER,      // local minima numbered, their records initialised
     C_PH_BASIN,       // descent chains followed to the local minimum
-    C_PH_CLEAR,       // pair table cleared
+    C_PH_CLEAR,       // field loads issued and the pair table cleared (from the workgroup's start)
     C_PH_INSERT,      // edges between basins marked and offered to the table
     C_PH_COMPACT,     // occupied table entries compacted
     C_PH_MERGE,       // merges of the kept edges (Alg. 3 in LDS)
@@ -534,12 +534,13 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
     __shared__ uint16_t zl[VOL];    // local minimum index of the vertex's local basin
     __shared__ uint64_t TL[HALF];   // triplets of the local minima
     __shared__ uint16_t mh[HALF];   // tile position of local minimum i
-    // The lowest-neighbour pointers are dead once the basins are known; the
-    // table takes their place.
-    __shared__ uint64_t htab[H];
+    __shared__ uint64_t htab[H];    // the pair table
+    // The lowest-neighbour pointers are dead once the basins are known, and
+    // the triplets' space is first written after that: the pointers live
+    // there, so that the table can be cleared while the field loads.
     typedef int16_t __attribute__((may_alias)) i16a;
-    i16a *const wl = (i16a *)htab;  // lowest lower neighbour in the tile (self at a local minimum)
-    static_assert(sizeof(int16_t) * VOL <= sizeof(uint64_t) * H, "aliasing");
+    i16a *const wl = (i16a *)TL;    // lowest lower neighbour in the tile (self at a local minimum)
+    static_assert(sizeof(int16_t) * VOL <= sizeof(uint64_t) * HALF, "aliasing");
     __shared__ uint32_t wsum[VOL / 64];
     __shared__ uint32_t sb0, nwin, scnt, novf;
     // edges that found no table room, merged with the table's entries (a
@@ -591,6 +592,9 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
             const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
             fv[k] = f[base + lid(min(lx, c.ex - 1), min(ly, c.ey - 1), min(lz, c.ez - 1))];
         }
+        // the pair table cleared while the loads are in flight
+        for (int i = threadIdx.x; i < H; i += NT) htab[i] = ~0ull;
+        phase(C_PH_CLEAR);
         bool nan = false;
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
@@ -730,9 +734,6 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
     }
     __syncthreads();
     phase(C_PH_BASIN);
-    for (int i = threadIdx.x; i < H; i += NT) htab[i] = ~0ull;
-    __syncthreads();
-    phase(C_PH_CLEAR);
 
     // Edges inside the tile whose ends lie in different local basins.  Of all
     // edges joining the same two basins only the lowest (smallest upper end)
