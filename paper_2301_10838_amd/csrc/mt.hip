@@ -428,14 +428,16 @@ static int enqueue_build(const Plan &p, const Ptrs &w, const float *f, void *T, 
                   (uint32_t)p.q_cap, w.slot, (const uint64_t *)w.mkey, n, p.cap, flip, w.h);
     const unsigned gm = (unsigned)std::min<int64_t>(8192, std::max<int64_t>(1, (p.m_cap + kBlock - 1) / kBlock));
     if (p.count == 1)
-        MT_LAUNCH("k_repair_min", k_repair_min<true>, dim3(gm), dim3(kBlock), st, f, w.slot, n, p.cap, flip, w.h);
+        MT_LAUNCH("k_repair_min", k_repair_min<true>, dim3(gm), dim3(kBlock), st, f, w.slot,
+                  (const uint64_t *)w.mkey, n, p.cap, flip, w.h);
     else
-        MT_LAUNCH("k_repair_min", k_repair_min<false>, dim3(gm), dim3(kBlock), st, f, w.slot, n, p.cap, flip, w.h);
+        MT_LAUNCH("k_repair_min", k_repair_min<false>, dim3(gm), dim3(kBlock), st, f, w.slot,
+                  (const uint64_t *)w.mkey, n, p.cap, flip, w.h);
     auto reg = [&](auto cnt, auto out) {
         using O = decltype(out);
         auto *const kern = &k_repair_reg<decltype(cnt)::value, O>;
         MT_LAUNCH("k_repair_reg", kern, dim3((unsigned)p.n_chunks), dim3(kBlock), st, f, (const uint32_t *)w.lbl,
-                  w.slot, (const uint64_t *)w.mkey, (typename O::Word *)T, w.pcnt,
+                  w.slot, (typename O::Word *)T, w.pcnt,
                   stage_pairs ? w.stage : nullptr, stage_pairs ? w.bcnt : nullptr, (const FieldDesc *)w.D,
                   (const int64_t *)w.cs, nf, n, p.cap, flip, w.h);
         return MT_OK;

@@ -1503,6 +1503,12 @@ __global__ __launch_bounds__(kBlock) void k_merge_q(const float *__restrict__ f,
 // ---------------------------------------------------------------------------
 // 3. Repair (Alg. 4, 5)
 
+// The id half of minimum m's key word (ids are the low 32 bits): one 4-byte load.
+__device__ __forceinline__ uint32_t mkey_id(const uint64_t *__restrict__ mkey, uint32_t m)
+{
+    return reinterpret_cast<const uint32_t *>(mkey)[2 * (size_t)m];
+}
+
 // Representative: follow the slots from x while the saddle is at or below
 // `level` and x is no root; the last minimum reached.
 template <bool CNT>
@@ -1523,8 +1529,16 @@ __device__ __forceinline__ uint32_t chase(Slot *__restrict__ S, const float *__r
     return x;
 }
 
+// Every minimum that is no root gets its repaired triplet, and its slot's
+// key word is rewritten as (value key of the saddle << 32) | the minimum's
+// own id, which is the form the output pass reads: the last slot of a chase
+// then names the vertex the chase ends at.  Chases of other lanes that meet
+// a rewritten word find its id half no longer equal to the saddle's id and
+// read the saddle's value from the field instead (a root's word, (own key),
+// is already in that form and stays).
 template <bool CNT>
-__global__ __launch_bounds__(kBlock) void k_repair_min(const float *__restrict__ f, Slot *__restrict__ S, uint32_t n,
+__global__ __launch_bounds__(kBlock) void k_repair_min(const float *__restrict__ f, Slot *__restrict__ S,
+                                                       const uint64_t *__restrict__ mkey, uint32_t n,
                                                        uint32_t cap, uint32_t flip, Header *__restrict__ h)
 {
     const uint32_t M = h->n_minima;
@@ -1536,8 +1550,10 @@ __global__ __launch_bounds__(kBlock) void k_repair_min(const float *__restrict__
         const uint32_t v = hi32(t.w), s = lo32(t.w);
         if (v == m) continue;
         if (v >= M || s >= n) { err |= ST_CORRUPT; continue; }
-        const uint32_t r = chase<CNT>(S, f, flip, M, n, v, saddle_key(t, f, flip), cap, err, tc);
+        const uint64_t ks = saddle_key(t, f, flip);
+        const uint32_t r = chase<CNT>(S, f, flip, M, n, v, ks, cap, err, tc);
         if (r != v) st_relaxed(&S[m].w, pack(s, r));
+        st_relaxed(&S[m].k, (uint64_t)((ks & 0xffffffff00000000ull) | mkey_id(mkey, m)));
     }
     if (err) atomicOr(&h->status, err);
     tc.flush(h);
@@ -1572,19 +1588,15 @@ constexpr int kStagePerChunk = (kBlock / 64) * kStageCap;    // entries per chun
 // its own (repaired) triplet; any other vertex u gets (u, u, representative
 // of its local minimum at the level of u).  Also counts pairs and roots per
 // chunk, and stages the pairs when `stage` is not null.  Slots are read-only
-// here, so plain loads; each lane carries RV vertices at once, so the
-// dependent loads of their chases (label -> slot -> slot ... -> minimum key)
-// overlap.
+// here, so plain loads, and repaired: a slot's key word holds (value key of
+// the saddle, the minimum's own id), so the last slot a chase reads names the
+// vertex the chase ends at.  Each lane carries RV vertices at once, so the
+// dependent loads of their chases (label -> slot -> slot ...) overlap.
 constexpr int RV = 4;
-// The id half of minimum m's key word (ids are the low 32 bits): one 4-byte load.
-__device__ __forceinline__ uint32_t mkey_id(const uint64_t *__restrict__ mkey, uint32_t m)
-{
-    return reinterpret_cast<const uint32_t *>(mkey)[2 * (size_t)m];
-}
 static_assert(kChunk == kBlock * RV * 4 && (kBlock / 64) * RV * 4 == kBuckets, "bucket layout");
 template <bool CNT, class O>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_repair_reg(const float *__restrict__ f, const uint32_t *__restrict__ lbl,
-                                                       const Slot *__restrict__ S, const uint64_t *__restrict__ mkey,
+                                                       const Slot *__restrict__ S,
                                                        typename O::Word *__restrict__ T, uint32_t *__restrict__ pcnt,
                                                        uint4 *__restrict__ stage, uint8_t *__restrict__ bcnt,
                                                        const FieldDesc *__restrict__ D, const int64_t *__restrict__ cs,
@@ -1608,9 +1620,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
         const int gi = (int)((g0 - lo) / (kBlock * RV));
         uint32_t u[RV], z[RV], x[RV], s[RV];
         uint64_t level[RV], tw[RV], tk[RV];
-        uint32_t mz[RV];  // id of the local minimum z (the low half of its key word)
-        // bit i: vertex i is written / chasing / gets target mkey[x[i]] (else itself: a root)
-        uint32_t live = 0, act = 0, need = 0;
+        // id of the vertex the target names: the low half of the key word of
+        // the last slot read (the repaired slots hold (saddle value, own id))
+        uint32_t tid[RV];
+        // bit i: vertex i is written / chasing / stops after one slot read /
+        // gets target tid[i] (else itself: a root)
+        uint32_t live = 0, act = 0, once = 0, need = 0;
 #pragma unroll
         for (int i = 0; i < RV; ++i) {
             const int64_t j = g0 + i * kBlock + threadIdx.x;
@@ -1627,7 +1642,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                 z[i] = 0;
                 live &= ~(1u << i);
             }
-            mz[i] = mkey_id(mkey, z[i]);
             tw[i] = S[z[i]].w;
             tk[i] = S[z[i]].k;
         }
@@ -1635,6 +1649,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
         for (int i = 0; i < RV; ++i) {
             x[i] = z[i];
             s[i] = u[i];
+            tid[i] = lo32(tk[i]);  // the local minimum z's own id
             const uint32_t s0 = lo32(tw[i]), v0 = hi32(tw[i]);
             bool pf = false;  // u is a pair birth (a live local minimum with s != u)
             uint32_t dk = 0;  // then: the value key of its saddle
@@ -1642,8 +1657,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                 if ((live >> i) & 1u) err |= ST_CORRUPT;
                 live &= ~(1u << i);
             } else {
-                const uint64_t sk = lo32(tk[i]) == s0 ? tk[i] : vkey(f, s0, flip);
-                if (mz[i] == u[i]) {  // u is a local minimum: its own repaired triplet
+                const uint64_t sk = ((uint64_t)hi32(tk[i]) << 32) | s0;
+                if (tid[i] == u[i]) {  // u is a local minimum: its own repaired triplet
                     s[i] = s0;
                     if ((live >> i) & 1u) {
                         // a root: one per connected component, so counted by a rare atomic
@@ -1651,8 +1666,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                         pf = s0 != u[i];
                         dk = hi32(sk);
                     }
-                    if (v0 != z[i]) {
+                    if (v0 != z[i]) {  // its target's id: one slot read
                         x[i] = v0;
+                        act |= 1u << i;
+                        once |= 1u << i;
                         need |= 1u << i;
                     }
                 } else if (v0 == z[i] || sk > level[i]) {
@@ -1702,19 +1719,18 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                     live &= ~(1u << i);
                     continue;
                 }
-                const uint64_t sk = lo32(tk[i]) == sv ? tk[i] : vkey(f, sv, flip);
-                if (v == x[i] || sk > level[i]) act &= ~(1u << i);
+                tid[i] = lo32(tk[i]);
+                const uint64_t sk = ((uint64_t)hi32(tk[i]) << 32) | sv;
+                if (((once >> i) & 1u) || v == x[i] || sk > level[i]) act &= ~(1u << i);
                 else x[i] = v;
             }
         }
 #pragma unroll
-        for (int i = 0; i < RV; ++i)
-            x[i] = ((need >> i) & 1u) ? mkey_id(mkey, x[i]) : u[i];  // the target's id
-#pragma unroll
         for (int i = 0; i < RV; ++i) {
             if (!((live >> i) & 1u)) continue;
-            if (x[i] >= n) { err |= ST_CORRUPT; continue; }
-            O::store(T, u[i], s[i] - off, x[i] - off);
+            const uint32_t t = ((need >> i) & 1u) ? tid[i] : u[i];  // the target's id
+            if (t >= n) { err |= ST_CORRUPT; continue; }
+            O::store(T, u[i], s[i] - off, t - off);
         }
     }
     if (lane == 0) sp[wave] = wcnt;
