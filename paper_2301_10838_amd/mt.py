@@ -178,7 +178,16 @@ def grid_dims(shape: Sequence[int]):
     raise ValueError("fields must be 1-D, 2-D or 3-D")
 
 
+_raw_stream = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+
+
 def _stream_ptr(device: torch.device) -> int:
+    """The current stream of `device` as a raw handle.  (The raw accessor
+    builds no Stream object: a few microseconds less per call, which the
+    autograd backward pays once per step.)"""
+    if _raw_stream is not None:
+        idx = device.index if device.index is not None else torch.cuda.current_device()
+        return int(_raw_stream(idx))
     return torch.cuda.current_stream(device).cuda_stream
 
 
@@ -485,7 +494,7 @@ class MergeTreePairs(torch.autograd.Function):
         grad = torch.empty(plan.n_total, dtype=torch.float32, device=dev)
         _check(load_library().mt_pairs_backward(plan._dims_c, len(plan.dims), offsets.data_ptr(), P,
                                                 birth.data_ptr(), death.data_ptr(), gb.data_ptr(), gd.data_ptr(),
-                                                grad.data_ptr(), 0, torch.cuda.current_stream(dev).cuda_stream),
+                                                grad.data_ptr(), 0, _stream_ptr(dev)),
                "mt_pairs_backward")
         return grad, None
 

@@ -131,3 +131,16 @@ def test_descent_loop_reduces_loss(dev):
         with torch.no_grad():
             flat -= 0.1 * x.grad
     assert losses[-1] < 0.5 * losses[0], losses
+
+
+def test_stream_handle_matches_torch():
+    """The binding's raw stream handle is torch's current stream, also on a
+    side stream (the backward enqueues on whatever stream autograd made current)."""
+    import paper_2301_10838_amd.mt as mt
+
+    dev = device()
+    assert mt._stream_ptr(dev) == torch.cuda.current_stream(dev).cuda_stream
+    s = torch.cuda.Stream(device=dev)
+    with torch.cuda.stream(s):
+        assert mt._stream_ptr(dev) == s.cuda_stream
+    assert mt._stream_ptr(torch.device("cuda")) == torch.cuda.current_stream().cuda_stream
