@@ -746,7 +746,6 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
     // is merged directly.
     uint32_t err = 0;
     const bool tabled = (uint32_t)HALF <= ZMAX || cnt <= ZMAX;
-    // the local minima's triplets: roots at their own level
     // The value keys of the local minima, for the table merges' test of
     // which minimum lies deeper, where a tile with a table (at most ZMAX
     // minima) leaves the triplets' upper half unused (shapes whose triplets
@@ -754,6 +753,7 @@ __global__ __launch_bounds__(S::NT, 8) void k_local(const float *__restrict__ f,
     constexpr bool MKV = (uint32_t)HALF > ZMAX;
     static_assert(!MKV || 2 * (HALF - ZMAX) >= ZMAX, "room for the minima's value keys");
     uint32_t *const mkv = reinterpret_cast<uint32_t *>(TL + (MKV ? ZMAX : 0));
+    // the local minima's triplets, roots at their own level (and their value keys)
     auto init_tl = [&]() {
         for (uint32_t i = threadIdx.x; i < cnt; i += NT) {
             const uint32_t mp = mh[i];
